@@ -1,0 +1,168 @@
+"""FP64 CPU oracle for the MVGD Laplace-Beltrami discretisation (arXiv:1603.04100).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()`` and by the
+CPU-baseline leg of ``bench.py``. The GPU library never imports or links it, and it shares no
+code with the GPU path. The arithmetic lives in ``mvgd_oracle.c`` (plain C, double, no FMA);
+this module only marshals numpy arrays through ctypes.
+
+Functions follow the paper's steps (see the header of ``mvgd_oracle.c``):
+
+* ``knn``     O1, brute force, ascending (key, index).
+* ``rows``    O1-O11 for a list of rows: MVGD (Sec. 3.1) or the plain least-squares variant
+              (Sec. 2), with optional per-row diagnostics.
+* ``assemble``  ``rows`` for every point, returned as CSR (row_ptr, cols, vals).
+* ``apply``   O12, y = L x.
+* ``lb_coefficients``  O8 alone: (G, q) of Eq. eqn3 from fitted graph coefficients.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mvgd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+ODIAG = 64
+
+# column layout of the per-row diagnostics returned by ``rows(..., diag=True)``
+DIAG_FIELDS = {
+    "h": 0, "degenerate": 1, "lam": slice(2, 6), "frame": slice(6, 22), "a": slice(22, 40),
+    "G": slice(40, 44), "q": slice(44, 46), "ell": slice(46, 52), "rdiag": slice(52, 58),
+    "tau": 58, "rcond": 59, "kth_key": 60,
+}
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, -ffp-contract=off, OpenMP over rows)."""
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.oracle_knn.argtypes = [P, i64, i32, i32, P, i64, P, P, i32]
+    lib.oracle_knn.restype = i32
+    lib.oracle_rows.argtypes = [P, i64, i32, i32, i32, i32, i32, f64, P, i64, P, P, P, i32]
+    lib.oracle_rows.restype = i32
+    lib.oracle_apply.argtypes = [i64, P, P, P, i32, P, P]
+    lib.oracle_apply.restype = i32
+    lib.oracle_lb_coefficients.argtypes = [i32, i32, P, P, P]
+    lib.oracle_lb_coefficients.restype = i32
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def _points(points):
+    p = np.ascontiguousarray(points, dtype=np.float64)
+    if p.ndim != 2:
+        raise ValueError("points must be [N, n]")
+    return p
+
+
+def _rows_arg(rows, n):
+    if rows is None:
+        return None, n
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    return r, r.shape[0]
+
+
+def knn(points, k: int, rows=None, nthreads: int = 0):
+    """K nearest neighbours (indices [R, K], keys [R, K]) ascending by (key, index)."""
+    p = _points(points)
+    r, nr = _rows_arg(rows, p.shape[0])
+    idx = np.empty((nr, k), dtype=np.int64)
+    key = np.empty((nr, k), dtype=np.float64)
+    rc = _load().oracle_knn(_ptr(p), p.shape[0], p.shape[1], k, _ptr(r), nr, _ptr(idx), _ptr(key),
+                            nthreads)
+    if rc != 0:
+        raise ValueError(f"oracle_knn failed ({rc})")
+    return idx, key
+
+
+def rows(points, k: int, rows=None, d: int = 2, variant: str = "mvgd", h_override=None,
+         diag: bool = False, nthreads: int = 0):
+    """MVGD rows (or the plain LS variant) for the given rows.
+
+    Returns (cols [R, K+1] int64 ascending, vals [R, K+1] float64[, diag [R, 64]]).
+    """
+    p = _points(points)
+    r, nr = _rows_arg(rows, p.shape[0])
+    cols = np.empty((nr, k + 1), dtype=np.int64)
+    vals = np.empty((nr, k + 1), dtype=np.float64)
+    dg = np.empty((nr, ODIAG), dtype=np.float64) if diag else None
+    var = {"mvgd": 0, "ls": 1}[variant]
+    use_h = 0 if h_override is None else 1
+    rc = _load().oracle_rows(_ptr(p), p.shape[0], p.shape[1], d, k, var, use_h,
+                             float(h_override or 0.0), _ptr(r), nr, _ptr(cols), _ptr(vals),
+                             _ptr(dg), nthreads)
+    if rc == -2:
+        raise ValueError("oracle_rows: non-finite coordinates")
+    if rc != 0:
+        raise ValueError(f"oracle_rows: invalid arguments ({rc})")
+    return (cols, vals, dg) if diag else (cols, vals)
+
+
+def assemble(points, k: int, d: int = 2, variant: str = "mvgd", h_override=None,
+             nthreads: int = 0):
+    """The whole matrix as CSR: (row_ptr int64 [N+1], cols int64 [nnz], vals float64 [nnz])."""
+    cols, vals = rows(points, k, None, d=d, variant=variant, h_override=h_override,
+                      nthreads=nthreads)
+    n = cols.shape[0]
+    row_ptr = np.arange(n + 1, dtype=np.int64) * (k + 1)
+    return row_ptr, cols.reshape(-1), vals.reshape(-1)
+
+
+def apply(row_ptr, cols, vals, x):
+    """y = L x (x: [N] or [N, R])."""
+    x = np.asarray(x, dtype=np.float64)
+    squeeze = x.ndim == 1
+    x2 = np.ascontiguousarray(x.reshape(x.shape[0], -1))
+    n = row_ptr.shape[0] - 1
+    y = np.empty((n, x2.shape[1]), dtype=np.float64)
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    v = np.ascontiguousarray(vals, dtype=np.float64)
+    _load().oracle_apply(n, _ptr(rp), _ptr(c), _ptr(v), x2.shape[1], _ptr(x2), _ptr(y))
+    return y[:, 0] if squeeze else y
+
+
+def lb_coefficients(a, d: int = 2):
+    """O8 alone: inverse metric G (d x d) and drift q (d) from the unscaled fit coefficients.
+
+    a: [n_codim, 6] (d = 2: a00, a10, a01, a20, a11, a02) or [n_codim, 3] (d = 1).
+    """
+    a = np.ascontiguousarray(np.atleast_2d(a), dtype=np.float64)
+    G = np.empty(d * d)
+    q = np.empty(d)
+    rc = _load().oracle_lb_coefficients(d, a.shape[0], _ptr(a), _ptr(G), _ptr(q))
+    if rc != 0:
+        raise ValueError("degenerate metric")
+    return G.reshape(d, d), q
