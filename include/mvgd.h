@@ -1,0 +1,169 @@
+/*
+ * mvgd.h -- C ABI of the MI355X (gfx950) implementation of the Modified Virtual Grid Difference
+ * (MVGD) discretisation of the Laplace-Beltrami operator on point clouds
+ * (M. Wang, S. Leung, H. Zhao, arXiv:1603.04100).
+ *
+ * Given a point cloud S = {p_i} sampling a d-dimensional manifold in R^n, mvgd_assemble builds,
+ * for every point, one row of a sparse matrix L whose entries are the weights of the point and its
+ * K nearest neighbours, so that (L U)_i approximates the Laplace-Beltrami operator of U at p_i
+ * (Sec. 2, problem statement and the assembled matrix A; Sec. 3.1, the MVGD). mvgd_apply computes
+ * y = L x. All work runs in HIP kernels on the device; the host only validates arguments, sizes
+ * the cell grids and enqueues work.
+ *
+ * Conventions shared by every entry point:
+ *  - Plain pointers and sizes only. Device buffers are device-resident memory (hipMalloc,
+ *    hipMallocAsync or a framework allocator); `stream` is a hipStream_t passed as void*, NULL for
+ *    the null stream. Work is stream-ordered: a call returns after enqueuing its kernels, except
+ *    where stated. The caller keeps inputs alive and unmodified until the stream has finished
+ *    the work that reads them.
+ *  - No call aborts the process. Every failure is reported by the return code; on failure no
+ *    handle is returned and nothing leaks. mvgd_last_error() gives a human-readable reason for the
+ *    most recent failure on the calling thread.
+ *  - Sign: L approximates +Delta (negative diagonal, rows summing to zero).
+ *  - Rows whose neighbourhood is degenerate (spacing h not positive and finite, or a rank-deficient
+ *    least-squares design: min |R_kk| < 1e-6 max |R_kk|) keep their columns and get zero values;
+ *    they are counted in mvgd_info_t.n_degenerate.
+ */
+#ifndef MVGD_H
+#define MVGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mvgd_matrix mvgd_matrix; /* opaque; owns the assembled matrix on one device */
+
+typedef enum {
+    MVGD_OK = 0,
+    MVGD_EINVAL = -1,      /* invalid argument (also: non-finite input coordinates) */
+    MVGD_ENOMEM = -2,      /* device or host allocation failed */
+    MVGD_EDEVICE = -3,     /* no usable device, or a HIP runtime error */
+    MVGD_EUNSUPPORTED = -4 /* valid for the method but not implemented on the GPU path */
+} mvgd_status;
+
+typedef enum {
+    MVGD_FP64 = 0,       /* points, weights and apply in double */
+    MVGD_FP32_MIXED = 1  /* points, weights and apply vectors in float; frame, covariance
+                            accumulation, least-squares solves and metric in double */
+} mvgd_precision;
+
+enum {
+    MVGD_FLAG_LS = 1u << 0,         /* plain least-squares discretisation (Sec. 2): derivatives
+                                       of the fitted quadratic at p_i, no centre modification */
+    MVGD_FLAG_H_OVERRIDE = 1u << 1, /* use params.h_override as the grid spacing of every row */
+    MVGD_FLAG_KEEP_DIAG = 1u << 2   /* keep per-row h and status bits for mvgd_row_diag */
+};
+
+typedef struct {
+    int32_t n_ambient;  /* n: 3 or 4 */
+    int32_t d_manifold; /* d: 2 (1 is reserved for curves and returns MVGD_EUNSUPPORTED) */
+    int32_t k;          /* K nearest neighbours: 5 <= K <= 63 and K < points in every cloud */
+    int32_t precision;  /* mvgd_precision */
+    uint32_t flags;     /* MVGD_FLAG_* */
+    double h_override;  /* > 0, used only with MVGD_FLAG_H_OVERRIDE */
+} mvgd_params;
+
+typedef struct {
+    int64_t n_rows;        /* rows = points over all clouds */
+    int32_t n_clouds;
+    int32_t k;
+    int64_t nnz;           /* n_rows * (k + 1) */
+    int32_t precision;     /* mvgd_precision */
+    int32_t n_ambient;
+    int64_t n_degenerate;  /* rows with zero values (see above) */
+    int64_t n_slow_knn;    /* rows whose neighbour search took the exhaustive fallback
+                              (exact ties or extreme clustering); informational */
+    size_t device_bytes;   /* device memory held by the handle */
+} mvgd_info_t;
+
+/*
+ * mvgd_assemble -- build L for one point cloud or a batch of clouds.
+ *
+ * Method (per point, Sec. 2 and Sec. 3.1): the K nearest neighbours N(i) in ambient Euclidean
+ * distance (ties to the smaller index); covariance of N(i) about its barycentre and its
+ * eigenvectors (PCA frame, the smallest eigenvalue's vectors are the normals); local coordinates
+ * of p_j - p_i; spacing h = 1/4 min over the tangent axes of the coordinate range over N(i)
+ * (Eq. DefH); least-squares quadratic fits over {p_i} u N(i) of each normal coordinate
+ * (Eq. poly) and of U (Eq. T); metric of the fitted graph (Eq. metric) giving the coefficients of
+ * Eq. eqn3; central differences on the virtual grid of spacing h with U_i at the centre node
+ * (Eq. centered1 and its higher-dimensional form).
+ *
+ * points        device, row-major [n_total, n_ambient]; float for MVGD_FP32_MIXED, double for
+ *               MVGD_FP64. Must be finite (non-finite values give MVGD_EINVAL).
+ * n_total       total number of points over all clouds (< 2^31).
+ * cloud_offsets HOST array int64[n_clouds + 1], offsets[0] = 0, strictly increasing,
+ *               offsets[n_clouds] = n_total; NULL means one cloud. Clouds are independent:
+ *               neighbours are searched inside each cloud only.
+ * n_clouds      >= 1 (ignored when cloud_offsets is NULL).
+ * p             parameters (see mvgd_params).
+ * stream        hipStream_t as void*.
+ * out           receives the handle on MVGD_OK, NULL otherwise.
+ *
+ * Synchronisation: after one reduction over the input (bounding box and finiteness per cloud) the
+ * call waits for `stream` once, so that it can reject non-finite input synchronously and size the
+ * cell grids exactly; all remaining work is enqueued on `stream` and the call returns without
+ * waiting for it. The handle may be used on `stream` at once, or on another stream after the
+ * caller has ordered that stream after `stream`.
+ */
+mvgd_status mvgd_assemble(const void *points, int64_t n_total, const int64_t *cloud_offsets,
+                          int32_t n_clouds, const mvgd_params *p, void *stream,
+                          mvgd_matrix **out);
+
+/*
+ * mvgd_apply -- y = L x (Sec. 2: each row is a linear combination of the point's and its
+ * neighbours' values), for nrhs right-hand sides at once.
+ *
+ * x, y  device, row-major [n_rows, nrhs], element type of the matrix (float for FP32-mixed,
+ *       double for FP64); rows are the caller's point order. y is overwritten; x and y must not
+ *       overlap. Sums accumulate in double.
+ * nrhs  1 <= nrhs <= 64.
+ * The handle keeps a staging buffer for the permuted x; calls on the same handle must be ordered
+ * (same stream, or ordered by the caller).
+ */
+mvgd_status mvgd_apply(mvgd_matrix *L, const void *x, void *y, int32_t nrhs, void *stream);
+
+/*
+ * mvgd_free -- release the handle and its device memory. Stream-ordered on the stream of the last
+ * assemble/apply/export call on this handle; NULL is accepted.
+ */
+void mvgd_free(mvgd_matrix *L);
+
+/*
+ * mvgd_csr -- write L in CSR form into caller-provided device buffers, in the caller's point order
+ * (Sec. 2, the assembled matrix): row i holds columns {i} u N(i) in ascending order with their
+ * weights, explicit zeros kept. Columns are local to each cloud (0-based within the cloud);
+ * row_ptr is global over the batch, row_ptr[i] = i * (K + 1).
+ *
+ * row_ptr int64[n_rows + 1], col int32[nnz], val float|double[nnz] (matrix element type).
+ * Any of the three may be NULL to skip it. Stream-ordered.
+ */
+mvgd_status mvgd_csr(mvgd_matrix *L, int64_t *row_ptr, int32_t *col, void *val, void *stream);
+
+/*
+ * mvgd_row_diag -- per-row diagnostics in the caller's point order, into caller device buffers:
+ * h (double[n_rows], the virtual grid spacing of Eq. DefH) and status (uint8[n_rows]: bit 0
+ * degenerate, bit 1 exhaustive neighbour-search fallback). Needs MVGD_FLAG_KEEP_DIAG at assembly,
+ * otherwise MVGD_EINVAL. Either pointer may be NULL. Stream-ordered.
+ */
+mvgd_status mvgd_row_diag(mvgd_matrix *L, double *h, uint8_t *status, void *stream);
+
+/* mvgd_info -- sizes and counters; waits for the handle's stream (synchronous). */
+mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info);
+
+/* Human-readable name of a status code (static string). */
+const char *mvgd_status_str(mvgd_status s);
+
+/* Reason for the most recent failure on the calling thread (static thread-local buffer). */
+const char *mvgd_last_error(void);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t mvgd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MVGD_H */

@@ -1,0 +1,823 @@
+// assemble.hpp -- fused per-point MVGD assembly: exact K nearest neighbours, PCA frame,
+// quadratic least-squares fits, metric, virtual-grid stencil, sliced-ELL write.
+//
+// Mapping: one wave (64 lanes) per group of 64 consecutive cell-sorted points; lane = point.
+// Because the points are sorted by Morton-ordered cell, a group is spatially compact and all
+// of its lanes search the same box of cells: the wave streams the box's points through LDS in
+// chunks of 64 (coalesced loads) and every lane reads each staged point as an LDS broadcast.
+//
+// Exact neighbour selection (the paper's "K nearest neighbours", Sec. 2; ties to the smaller
+// index, the exact key being the FP64 sum ((d0^2 + d1^2) + d2^2) + d3^2 without contraction):
+//   pass 1  per-lane histogram (64 bins, 16-bit counters in LDS) of the squared distance f over
+//           [0, R^2], R the radius the box guarantees; grows the box until every lane counts K.
+//   refine  optional second histogram inside the bin holding the K-th neighbour.
+//   pass 2  with e = 4e-6 bounding |f - key|/key: f(1+e) < lo(1-e) is surely in (written to the
+//           list); f(1-e) <= hi(1+e) is a boundary candidate, re-keyed exactly in FP64.
+//   resolve the (K - #sure) smallest boundary candidates by (key, index), ranked in LDS.
+//   slow    lanes whose boundary overflows (exact ties, extreme clustering) extract the missing
+//           neighbours one at a time by (key, index) over repeated streams.
+//
+// Fit (per lane, Sec. 2 and Sec. 3.1): covariance of N(i) about its barycentre accumulated in
+// FP64 from exact differences; cyclic Jacobi in FP64 (frame: the two largest eigenvalues are
+// tangent, the rest normal); local coordinates and the spacing h = 1/4 min tangent range
+// (Eq. DefH); design monomials of (u/h) over {p_i} u N(i); Gram matrix accumulated in FP64;
+// Cholesky in FP64; fits of the normal coordinates (Eq. poly); inverse metric G and drift q
+// of the fitted graph (Eq. metric, Eq. eqn3); ell = (tau, -q1, -q2, 2G11, 2G12, 2G22),
+// tau = 2 (G11 + G22)/h^2 (centre value U_i in the virtual-grid differences, Eq. centered1);
+// y = Gram^-1 D ell with one FP64 refinement step on V^T w = D ell; w = V y, w_centre -= tau.
+#pragma once
+
+#include "common.hpp"
+
+namespace mvgd {
+
+struct AsmParams {
+    const void *spts;           // Pt<T>[n_total], cell-sorted
+    const int32_t *perm;        // sorted position -> global row
+    const uint32_t *cell_start; // global cell table, exclusive prefix (cells + 1)
+    const uint32_t *parts;      // Morton part tables
+    const CloudGrid *grids;
+    int32_t n_clouds;
+    int32_t K;
+    int64_t n_groups;
+    int64_t groups_per_xcd;     // XCD-aware remap of workgroups to groups
+    int32_t variant;            // 0 = MVGD, 1 = plain least squares
+    int32_t use_h;
+    double h_override;
+    int64_t ld;                 // sliced-ELL leading dimension
+    int32_t *ell_col;           // [K+1][ld] sorted positions
+    void *ell_val;              // [K+1][ld] weights (T)
+    double *row_h;              // optional, sorted order
+    uint8_t *row_flags;         // optional, sorted order
+    unsigned long long *counters; // [0] degenerate rows, [1] slow-path rows, [2] internal errors
+};
+
+// LDS layout of one wave (bytes)
+constexpr int kLdsHist = 0;                                 // u32 [kBinWords][64] | f64 [kBndCap][64]
+constexpr int kLdsBndPos = kLdsHist + kBndCap * kWave * 8;  // i32 [kBndCap][64]
+constexpr int kLdsList = kLdsBndPos + kBndCap * kWave * 4;  // i32 [K][64]
+static_assert(kBinWords * kWave * 4 <= kBndCap * kWave * 8, "histogram must fit the key area");
+
+__host__ __device__ constexpr int lds_bytes(int K, int pt_bytes)
+{
+    return kLdsList + K * kWave * 4 /*list*/ + 2 * kWave * 4 /*cell ranges*/ +
+           kWave * pt_bytes + 2 * kWave * 4 /*staged pos, idx*/;
+}
+
+template <typename T, int NA>
+__device__ __forceinline__ double exact_key(const Pt<T> &q, const Pt<T> &c)
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        double d = (double)c.v[k] - (double)q.v[k];
+        double sq = d * d;
+        s = (k == 0) ? sq : s + sq;
+    }
+    return s;
+}
+
+// squared distance used for culling: FP32 for float points, the exact key rounded for doubles
+template <typename T, int NA>
+__device__ __forceinline__ float cull_dist(const Pt<T> &q, const Pt<T> &c);
+
+template <>
+__device__ __forceinline__ float cull_dist<float, 3>(const Pt<float> &q, const Pt<float> &c)
+{
+    float d0 = c.v[0] - q.v[0], d1 = c.v[1] - q.v[1], d2 = c.v[2] - q.v[2];
+    return fmaf(d2, d2, fmaf(d1, d1, d0 * d0));
+}
+template <>
+__device__ __forceinline__ float cull_dist<float, 4>(const Pt<float> &q, const Pt<float> &c)
+{
+    float d0 = c.v[0] - q.v[0], d1 = c.v[1] - q.v[1], d2 = c.v[2] - q.v[2], d3 = c.v[3] - q.v[3];
+    return fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
+}
+template <>
+__device__ __forceinline__ float cull_dist<double, 3>(const Pt<double> &q, const Pt<double> &c)
+{
+    return (float)exact_key<double, 3>(q, c);
+}
+template <>
+__device__ __forceinline__ float cull_dist<double, 4>(const Pt<double> &q, const Pt<double> &c)
+{
+    return (float)exact_key<double, 4>(q, c);
+}
+
+// Stream every point of the cell box [bmin, bmax] of cloud g through LDS, 64 at a time, and call
+// visit(point, sorted position, original index) on every lane for every point.
+template <typename T, typename F>
+__device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &g, const int bmin[3],
+                                           const int bmax[3], char *lds_rng, char *lds_stage,
+                                           F &&visit)
+{
+    const int lane = lane_id();
+    const Pt<T> *spts = (const Pt<T> *)P.spts;
+    int32_t *rng_start = (int32_t *)lds_rng;
+    int32_t *rng_pref = rng_start + kWave;
+    Pt<T> *st_pt = (Pt<T> *)lds_stage;
+    int32_t *st_pos = (int32_t *)(lds_stage + kWave * sizeof(Pt<T>));
+    int32_t *st_idx = st_pos + kWave;
+    const int nx = bmax[0] - bmin[0] + 1, ny = bmax[1] - bmin[1] + 1, nz = bmax[2] - bmin[2] + 1;
+    const int nyz = ny * nz, ncells = nx * nyz;
+    for (int cb = 0; cb < ncells; cb += kWave) {
+        const int t = cb + lane;
+        uint32_t st = 0, cn = 0;
+        if (t < ncells) {
+            const int x = (int)((uint32_t)t / (uint32_t)nyz);
+            const int r = t - x * nyz;
+            const int y = (int)((uint32_t)r / (uint32_t)nz);
+            const int z = r - y * nz;
+            const uint32_t cell =
+                (uint32_t)g.cell0 + morton_of(P.parts, g, bmin[0] + x, bmin[1] + y, bmin[2] + z);
+            st = P.cell_start[cell];
+            cn = P.cell_start[cell + 1] - st;
+        }
+        const int incl = wave_incl_scan((int)cn);
+        const int total = __shfl(incl, kWave - 1, kWave);
+        rng_start[lane] = (int32_t)st;
+        rng_pref[lane] = incl - (int)cn;
+        __syncthreads();
+        for (int sb = 0; sb < total; sb += kWave) {
+            const int tt = sb + lane;
+            if (tt < total) {
+                int lo = 0, hi = kWave - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (rng_pref[mid] <= tt)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                const int pos = rng_start[lo] + (tt - rng_pref[lo]);
+                st_pt[lane] = spts[pos];
+                st_pos[lane] = pos;
+                st_idx[lane] = P.perm[pos];
+            }
+            __syncthreads();
+            const int nst = min(kWave, total - sb);
+            for (int j = 0; j < nst; ++j)
+                visit(st_pt[j], st_pos[j], st_idx[j]);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// small dense FP64 kernels (per lane, fully unrolled)
+// ---------------------------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void jacobi_eig(double A[N][N], double W[N][N])
+{
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c)
+            W[r][c] = (r == c) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        double off = 0.0, dia = 0.0;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+            dia += A[p][p] * A[p][p];
+#pragma unroll
+            for (int q = p + 1; q < N; ++q)
+                off += A[p][q] * A[p][q];
+        }
+        const bool done = !(off > 1e-34 * dia);
+        if (__ballot(!done) == 0)
+            break;
+#pragma unroll
+        for (int p = 0; p < N; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < N; ++q) {
+                const double apq = A[p][q];
+                double c = 1.0, s = 0.0;
+                if (apq != 0.0) {
+                    const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+                    double t = 1.0 / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
+                    t = theta < 0.0 ? -t : t;
+                    c = 1.0 / sqrt(fma(t, t, 1.0));
+                    s = t * c;
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const double wkp = W[k][p], wkq = W[k][q];
+                    W[k][p] = c * wkp - s * wkq;
+                    W[k][q] = s * wkp + c * wkq;
+                }
+            }
+        }
+    }
+}
+
+// packed upper triangle of a 6x6 symmetric matrix: index of (i, j), i <= j
+__host__ __device__ constexpr int sym6(int i, int j)
+{
+    return i * 6 - i * (i - 1) / 2 + (j - i);
+}
+
+// In-place Cholesky G = L L^T (L stored in the same packed slots, L(j,i) at sym6(i,j)).
+// Returns false when a pivot is not positive or min L_ii < 1e-6 max L_ii.
+__device__ __forceinline__ bool chol6(double G[21], double inv_diag[6])
+{
+    double dmin = INFINITY, dmax = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double s = G[sym6(i, i)];
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+            s -= G[sym6(k, i)] * G[sym6(k, i)];
+        ok = ok && (s > 0.0);
+        const double lii = sqrt(s > 0.0 ? s : 0.0);
+        G[sym6(i, i)] = lii;
+        inv_diag[i] = lii > 0.0 ? 1.0 / lii : 0.0;
+        dmin = fmin(dmin, lii);
+        dmax = fmax(dmax, lii);
+#pragma unroll
+        for (int j = i + 1; j < 6; ++j) {
+            double t = G[sym6(i, j)];
+#pragma unroll
+            for (int k = 0; k < i; ++k)
+                t -= G[sym6(k, j)] * G[sym6(k, i)];
+            G[sym6(i, j)] = t * inv_diag[i]; // L(j, i)
+        }
+    }
+    return ok && (dmin >= 1e-6 * dmax) && isfinite(dmax);
+}
+
+// solve (L L^T) x = b in place
+__device__ __forceinline__ void chol6_solve(const double L[21], const double inv_diag[6], double b[6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+            s -= L[sym6(k, i)] * b[k];
+        b[i] = s * inv_diag[i];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double s = b[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; ++k)
+            s -= L[sym6(i, k)] * b[k];
+        b[i] = s * inv_diag[i];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void monomials(T xi, T eta, double m[6])
+{
+    m[0] = 1.0;
+    m[1] = (double)xi;
+    m[2] = (double)eta;
+    m[3] = (double)(xi * xi);
+    m[4] = (double)(xi * eta);
+    m[5] = (double)(eta * eta);
+}
+
+// ---------------------------------------------------------------------------------------------
+// the kernel
+// ---------------------------------------------------------------------------------------------
+template <typename T, int NA>
+__global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
+{
+    constexpr int NC = NA - 2; // normal coordinates
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int lane = lane_id();
+    const int K = P.K;
+    char *lds_rng = lds + kLdsList + K * kWave * 4;
+    char *lds_stage = lds_rng + 2 * kWave * 4;
+    uint32_t *hist = (uint32_t *)(lds + kLdsHist);
+    double *bndkey = (double *)(lds + kLdsHist);
+    int32_t *bndpos = (int32_t *)(lds + kLdsBndPos);
+    int32_t *list = (int32_t *)(lds + kLdsList);
+
+    // XCD-aware remap: consecutive groups (neighbouring space) go to the same XCD / L2.
+    const int64_t b = blockIdx.x;
+    const int64_t group = (b & 7) * P.groups_per_xcd + (b >> 3);
+    if (group >= P.n_groups)
+        return;
+    int ci = 0;
+    {
+        int lo = 0, hi = P.n_clouds - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (P.grids[mid].group0 <= group)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        ci = lo;
+    }
+    const CloudGrid g = P.grids[ci];
+    const Pt<T> *spts = (const Pt<T> *)P.spts;
+    const int64_t s0 = g.row0 + (group - g.group0) * kWave;
+    const int cnt = (int)min((int64_t)kWave, g.row0 + g.n - s0);
+    const bool valid = lane < cnt;
+    const int q = (int)(s0 + (valid ? lane : 0));
+    const Pt<T> qp = spts[q];
+    int cc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int ax = g.axis[a];
+        const T xa = ax == 0 ? qp.v[0] : ax == 1 ? qp.v[1] : ax == 2 ? qp.v[2] : qp.v[3];
+        cc[a] = cell_coord<T>(xa, g.lo[a], g.inv_cell, g.dim[a]);
+    }
+    // every list slot holds a valid position before selection writes it
+    for (int k = 0; k < K; ++k)
+        list[k * kWave + lane] = q;
+
+    // ----- sub-group size: split while the search box of a sub-group is too large -------------
+    int S = kWave;
+    int mn[3], mx[3];
+    for (;;) {
+        int cells = 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mn[a] = seg_min(valid ? cc[a] : 0x3fffffff, S);
+            mx[a] = seg_max(valid ? cc[a] : -1, S);
+            const int lo = max(mn[a] - g.m0, 0), hi = min(mx[a] + g.m0, g.dim[a] - 1);
+            cells *= max(hi - lo + 1, 1);
+        }
+        const int worst = seg_max(valid ? cells : 0, kWave);
+        if (worst <= kMaxBoxCells || S <= 8)
+            break;
+        S >>= 1;
+    }
+
+    bool slow_row = false;
+    const float e = kRelBand;
+    for (int sg = 0; sg < kWave / S; ++sg) {
+        const int lead = sg * S;
+        if (lead >= cnt)
+            break;
+        const bool act = valid && (lane / S == sg);
+        int bmn[3], bmx[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            bmn[a] = __shfl(mn[a], lead, kWave);
+            bmx[a] = __shfl(mx[a], lead, kWave);
+        }
+        // ----- pass 1: histogram; grow the box until every active lane counts K ------------
+        int m = g.m0;
+        int box_lo[3], box_hi[3];
+        float R2 = 0.f, s0b = 0.f;
+        int total = 0;
+        for (;;) {
+            bool all = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                box_lo[a] = max(bmn[a] - m, 0);
+                box_hi[a] = min(bmx[a] + m, g.dim[a] - 1);
+                all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
+            }
+            const double rs = ((double)m - 0.01) * g.cell;
+            const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : rs * rs * (1.0 - 1e-5);
+            R2 = (float)R2d;
+            if (!all)
+                R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
+            R2 = fmaxf(R2, 1e-30f);
+            s0b = (float)kBins / R2;
+            for (int w = 0; w < kBinWords; ++w)
+                hist[w * kWave + lane] = 0u;
+            total = 0;
+            __syncthreads();
+            stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+                          [&](const Pt<T> &c, int pos, int idx) {
+                              if (!act || pos == q)
+                                  return;
+                              const float f = cull_dist<T, NA>(qp, c);
+                              if (f <= R2) {
+                                  ++total;
+                                  const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
+                                  atomicAdd(&hist[(bb >> 1) * kWave + lane], 1u << ((bb & 1) * 16));
+                              }
+                          });
+            const bool short_lane = act && total < K;
+            if (__ballot(short_lane) == 0 || all) {
+                if (short_lane)
+                    atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
+                break;
+            }
+            m += max(1, m / 2);
+        }
+
+        // ----- locate the bin of the K-th neighbour ------------------------------------------
+        const bool overflow = total >= 0xffff; // 16-bit counters saturated: exhaustive path
+        int below = 0, b0 = kBins - 1, in_b0 = 0;
+        {
+            int cum = 0;
+            bool found = false;
+            for (int w = 0; w < kBinWords; ++w) {
+                const uint32_t h = hist[w * kWave + lane];
+                const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                if (!found) {
+                    if (cum + c0 >= K) {
+                        found = true; b0 = 2 * w; below = cum; in_b0 = c0;
+                    } else if (cum + c0 + c1 >= K) {
+                        found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
+                    }
+                    cum += c0 + c1;
+                }
+            }
+        }
+        const float wb = R2 / (float)kBins;
+        float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
+        // ----- optional refinement inside bin b0 ---------------------------------------------
+        const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
+        if (__ballot(refine) != 0) {
+            const float base_lo = lo_f;
+            const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
+            for (int w = 0; w < kBinWords; ++w)
+                hist[w * kWave + lane] = 0u;
+            __syncthreads();
+            stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+                          [&](const Pt<T> &c, int pos, int idx) {
+                              if (!refine || pos == q)
+                                  return;
+                              const float f = cull_dist<T, NA>(qp, c);
+                              if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
+                                  return;
+                              int sb = (int)((f - base_lo) * s1);
+                              sb = sb < 0 ? 0 : (sb > kBins - 1 ? kBins - 1 : sb);
+                              atomicAdd(&hist[(sb >> 1) * kWave + lane], 1u << ((sb & 1) * 16));
+                          });
+            if (refine) {
+                int cum = below, b1 = kBins - 1;
+                bool found = false;
+                for (int w = 0; w < kBinWords; ++w) {
+                    const uint32_t h = hist[w * kWave + lane];
+                    const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                    if (!found) {
+                        if (cum + c0 >= K) {
+                            found = true; b1 = 2 * w;
+                        } else if (cum + c0 + c1 >= K) {
+                            found = true; b1 = 2 * w + 1;
+                        }
+                        cum += c0 + c1;
+                    }
+                }
+                const float w1 = (hi_f - base_lo) / (float)kBins;
+                const float nlo = base_lo + (float)b1 * w1;
+                const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
+                lo_f = nlo;
+                hi_f = nhi;
+            }
+        }
+        if (overflow) { // everything within R is a boundary candidate
+            lo_f = 0.f;
+            hi_f = R2;
+        }
+        // ----- pass 2: classify --------------------------------------------------------------
+        const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
+        int nin = 0, nb = 0;
+        stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+                      [&](const Pt<T> &c, int pos, int idx) {
+                          if (!act || pos == q)
+                              return;
+                          const float f = cull_dist<T, NA>(qp, c);
+                          if (f * (1.f + e) < lo_t) {
+                              if (nin < K)
+                                  list[nin * kWave + lane] = pos;
+                              ++nin;
+                          } else if (f * (1.f - e) <= hi_t) {
+                              if (nb < kBndCap) {
+                                  bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
+                                  bndpos[nb * kWave + lane] = pos;
+                              }
+                              ++nb;
+                          }
+                      });
+        if (act && nin >= K)
+            atomicAdd(&P.counters[2], 1ull); // cannot happen (fewer than K below the K-th bin)
+        const int r = K - nin;
+        const bool slow = act && (nb > kBndCap || nb < r || nin >= K);
+        // ----- resolve the boundary by exact (key, index) rank --------------------------------
+        if (act && !slow) {
+            for (int bi = 0; bi < nb; ++bi) {
+                const double kb = bndkey[bi * kWave + lane];
+                const int pb = bndpos[bi * kWave + lane];
+                int rank = 0;
+                for (int bj = 0; bj < nb; ++bj) {
+                    const double kj = bndkey[bj * kWave + lane];
+                    if (kj < kb)
+                        ++rank;
+                    else if (kj == kb && bj != bi && P.perm[bndpos[bj * kWave + lane]] < P.perm[pb])
+                        ++rank;
+                }
+                if (rank < r)
+                    list[(nin + rank) * kWave + lane] = pb;
+            }
+        }
+        // ----- exhaustive extraction for lanes that need it ----------------------------------
+        if (__ballot(slow) != 0) {
+            const int nin_s = slow ? (nin < K ? nin : 0) : 0;
+            const int rr = slow ? K - nin_s : 0;
+            const float lo_s = (slow && nin < K) ? lo_t : 0.f;
+            const int rmax = seg_max(rr, kWave);
+            double last_k = -1.0;
+            int last_i = -1;
+            for (int sidx = 0; sidx < rmax; ++sidx) {
+                double best_k = INFINITY;
+                int best_i = 0x7fffffff, best_p = -1;
+                const bool want = slow && sidx < rr;
+                stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+                              [&](const Pt<T> &c, int pos, int idx) {
+                                  if (!want || pos == q)
+                                      return;
+                                  const float f = cull_dist<T, NA>(qp, c);
+                                  if (f * (1.f + e) < lo_s || f * (1.f - e) > hi_t)
+                                      return;
+                                  const double k = exact_key<T, NA>(qp, c);
+                                  const bool after = k > last_k || (k == last_k && idx > last_i);
+                                  const bool better = k < best_k || (k == best_k && idx < best_i);
+                                  if (after && better) {
+                                      best_k = k; best_i = idx; best_p = pos;
+                                  }
+                              });
+                if (want) {
+                    if (best_p < 0)
+                        best_p = q;
+                    list[(nin_s + sidx) * kWave + lane] = best_p;
+                    last_k = best_k;
+                    last_i = best_i;
+                    if (best_i == 0x7fffffff)
+                        atomicAdd(&P.counters[2], 1ull);
+                }
+            }
+            if (slow)
+                slow_row = true;
+        }
+        __syncthreads();
+    }
+
+    // =============================== per-lane fit =============================================
+    if (!valid)
+        return;
+    T *val = (T *)P.ell_val;
+    double qd[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        qd[a] = (double)qp.v[a];
+
+    // covariance about the barycentre of N(i) (p_i excluded), FP64 from exact differences
+    double s1[NA], s2[NA][NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        s1[a] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c)
+            s2[a][c] = 0.0;
+    }
+    for (int k = 0; k < K; ++k) {
+        const Pt<T> pj = spts[list[k * kWave + lane]];
+        double dv[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            dv[a] = (double)pj.v[a] - qd[a];
+            s1[a] += dv[a];
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int c = a; c < NA; ++c)
+                s2[a][c] = fma(dv[a], dv[c], s2[a][c]);
+    }
+    const double invK = 1.0 / (double)K;
+    double A[NA][NA], W[NA][NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int c = a; c < NA; ++c) {
+            A[a][c] = s2[a][c] - s1[a] * s1[c] * invK;
+            A[c][a] = A[a][c];
+        }
+    jacobi_eig<NA>(A, W);
+    double lam[NA];
+    int rank[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        lam[a] = A[a][a];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        rank[a] = 0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c)
+            rank[a] += (c != a) && (lam[c] > lam[a] || (lam[c] == lam[a] && c < a));
+    }
+    T tf[2][NA], nf[NC][NA];
+    double lam_t[2] = {0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+            if (rank[a] == t)
+                lam_t[t] = lam[a];
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            const T v = (T)W[r][a];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                if (rank[a] == t)
+                    tf[t][r] = v;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (rank[a] == 2 + c)
+                    nf[c][r] = v;
+        }
+    }
+
+    // local coordinates and the spacing h (Eq. DefH)
+    T umin0 = (T)INFINITY, umax0 = -(T)INFINITY, umin1 = (T)INFINITY, umax1 = -(T)INFINITY;
+    for (int k = 0; k < K; ++k) {
+        const Pt<T> pj = spts[list[k * kWave + lane]];
+        T u0 = 0, u1 = 0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const T d = pj.v[a] - qp.v[a];
+            u0 += tf[0][a] * d;
+            u1 += tf[1][a] * d;
+        }
+        umin0 = min(umin0, u0); umax0 = max(umax0, u0);
+        umin1 = min(umin1, u1); umax1 = max(umax1, u1);
+    }
+    const T hT = (T)0.25 * min(umax0 - umin0, umax1 - umin1);
+    double h = P.use_h ? P.h_override : (double)hT;
+    bool degenerate = !(h > 0.0) || !isfinite(h);
+    const T ih = degenerate ? (T)0 : (T)(1.0 / h);
+
+    // Gram matrix of the design over {p_i} u N(i) and right-hand sides of the surface fits
+    double Gm[21], rz[NC][6];
+#pragma unroll
+    for (int t = 0; t < 21; ++t)
+        Gm[t] = 0.0;
+    Gm[0] = 1.0; // centre row (1, 0, 0, 0, 0, 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+            rz[c][t] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const Pt<T> pj = spts[list[k * kWave + lane]];
+        T u0 = 0, u1 = 0, z[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            z[c] = 0;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const T d = pj.v[a] - qp.v[a];
+            u0 += tf[0][a] * d;
+            u1 += tf[1][a] * d;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                z[c] += nf[c][a] * d;
+        }
+        double mv[6];
+        monomials<T>(u0 * ih, u1 * ih, mv);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j = i; j < 6; ++j)
+                Gm[sym6(i, j)] = fma(mv[i], mv[j], Gm[sym6(i, j)]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double zc = (double)z[c];
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+                rz[c][i] = fma(mv[i], zc, rz[c][i]);
+        }
+    }
+    double inv_d[6];
+    if (!degenerate)
+        degenerate = !chol6(Gm, inv_d);
+
+    double y[6] = {0, 0, 0, 0, 0, 0}, tau = 0.0;
+    if (!degenerate) {
+        const double ihd = 1.0 / h, ih2 = ihd * ihd;
+        const double scale[6] = {1.0, ihd, ihd, ih2, ih2, ih2};
+        // fitted graph of every normal coordinate (Eq. poly), unscaled coefficients
+        double g11 = 1.0, g12 = 0.0, g22 = 1.0;
+        double zx[NC], zy[NC], h11[NC], h12[NC], h22[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            chol6_solve(Gm, inv_d, rz[c]);
+            zx[c] = rz[c][1] * scale[1];
+            zy[c] = rz[c][2] * scale[2];
+            h11[c] = 2.0 * rz[c][3] * scale[3];
+            h12[c] = rz[c][4] * scale[4];
+            h22[c] = 2.0 * rz[c][5] * scale[5];
+            g11 = fma(zx[c], zx[c], g11);
+            g12 = fma(zx[c], zy[c], g12);
+            g22 = fma(zy[c], zy[c], g22);
+        }
+        // inverse metric (Eq. metric) and the first-order coefficients of Eq. eqn3
+        const double det = g11 * g22 - g12 * g12;
+        const double idet = 1.0 / det;
+        const double G11 = g22 * idet, G12 = -g12 * idet, G22 = g11 * idet;
+        double q1 = 0.0, q2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double tr = G11 * h11[c] + 2.0 * G12 * h12[c] + G22 * h22[c];
+            q1 = fma(tr, G11 * zx[c] + G12 * zy[c], q1);
+            q2 = fma(tr, G12 * zx[c] + G22 * zy[c], q2);
+        }
+        tau = (P.variant == 0) ? 2.0 * (G11 + G22) * ih2 : 0.0;
+        const double ell[6] = {tau, -q1, -q2, 2.0 * G11, 2.0 * G12, 2.0 * G22};
+        double dl[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            dl[t] = ell[t] * scale[t];
+            y[t] = dl[t];
+        }
+        chol6_solve(Gm, inv_d, y);
+        degenerate = !(det > 0.0) || !isfinite(tau) || !isfinite(y[0]);
+        if (sizeof(T) == 8 && !degenerate) {
+            // one refinement step on V^T w = D ell with the residual formed from V itself
+            double res[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+                res[t] = dl[t];
+            res[0] -= y[0]; // centre row e1: (V y)_0 = y0
+            for (int k = 0; k < K; ++k) {
+                const Pt<T> pj = spts[list[k * kWave + lane]];
+                T u0 = 0, u1 = 0;
+#pragma unroll
+                for (int a = 0; a < NA; ++a) {
+                    const T d = pj.v[a] - qp.v[a];
+                    u0 += tf[0][a] * d;
+                    u1 += tf[1][a] * d;
+                }
+                double mv[6];
+                monomials<T>(u0 * ih, u1 * ih, mv);
+                double w = 0.0;
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    w = fma(mv[t], y[t], w);
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    res[t] = fma(-w, mv[t], res[t]);
+            }
+            chol6_solve(Gm, inv_d, res);
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+                y[t] += res[t];
+        }
+    }
+
+    // weights w = V y (centre: y0 - tau) into the sliced ELL, slot 0 = centre
+    const int64_t ld = P.ld;
+    P.ell_col[q] = q;
+    val[q] = degenerate ? (T)0 : (T)(y[0] - tau);
+    for (int k = 0; k < K; ++k) {
+        const int pos = list[k * kWave + lane];
+        double w = 0.0;
+        if (!degenerate) {
+            const Pt<T> pj = spts[pos];
+            T u0 = 0, u1 = 0;
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const T d = pj.v[a] - qp.v[a];
+                u0 += tf[0][a] * d;
+                u1 += tf[1][a] * d;
+            }
+            double mv[6];
+            monomials<T>(u0 * ih, u1 * ih, mv);
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+                w = fma(mv[t], y[t], w);
+        }
+        P.ell_col[(int64_t)(k + 1) * ld + q] = pos;
+        val[(int64_t)(k + 1) * ld + q] = (T)w;
+    }
+    if (P.row_h)
+        P.row_h[q] = h;
+    if (P.row_flags)
+        P.row_flags[q] = (uint8_t)((degenerate ? 1 : 0) | (slow_row ? 2 : 0) |
+                                   ((lam_t[0] - lam_t[1]) < 1e-3 * lam_t[0] ? 4 : 0));
+    const unsigned long long nd = __popcll(__ballot(degenerate));
+    const unsigned long long ns = __popcll(__ballot(slow_row));
+    if (lane == __ffsll((long long)__ballot(true)) - 1) {
+        if (nd)
+            atomicAdd(&P.counters[0], nd);
+        if (ns)
+            atomicAdd(&P.counters[1], ns);
+    }
+}
+
+} // namespace mvgd

@@ -1,0 +1,200 @@
+// bin.hpp -- counting sort of the points into Morton-ordered cells (the neighbour-search grid).
+//
+// bbox_kernel      per-cloud bounding box over all ambient coordinates + non-finite count
+// key_kernel       cell key of every point and its slot inside the cell (atomic count)
+// scan_*           exclusive prefix sum of the cell counts -> cell start offsets
+// scatter_kernel   cell-sorted copy of the points (padded to 4 components) + permutation
+#pragma once
+
+#include "common.hpp"
+
+namespace mvgd {
+
+struct CloudStats {  // ordered-encoded doubles; see ord_encode
+    unsigned long long mn[4];
+    unsigned long long mx[4];
+    unsigned long long nonfinite;
+    unsigned long long pad[7];
+};
+
+__global__ void stats_init_kernel(CloudStats *st, int n_clouds)
+{
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_clouds)
+        return;
+    for (int a = 0; a < 4; ++a) {
+        st[c].mn[a] = ~0ull;
+        st[c].mx[a] = 0ull;
+    }
+    st[c].nonfinite = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts, int n_amb,
+                                                   const int64_t *__restrict__ offsets,
+                                                   CloudStats *st)
+{
+    const int c = blockIdx.y;
+    const int64_t b = offsets[c], e = offsets[c + 1];
+    double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+    double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    unsigned long long bad = 0;
+    for (int64_t i = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < e;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int a = 0; a < n_amb; ++a) {
+            double v = (double)pts[i * n_amb + a];
+            if (!isfinite(v)) {
+                ++bad;
+                continue;
+            }
+            mn[a] = fmin(mn[a], v);
+            mx[a] = fmax(mx[a], v);
+        }
+    }
+    __shared__ double smn[4][4], smx[4][4];
+    __shared__ unsigned long long sbad[4];
+    const int w = threadIdx.x / kWave, l = lane_id();
+    for (int a = 0; a < 4; ++a) {
+        mn[a] = seg_min(mn[a], kWave);
+        mx[a] = seg_max(mx[a], kWave);
+    }
+    bad = wave_sum(bad);
+    if (l == 0) {
+        for (int a = 0; a < 4; ++a) {
+            smn[w][a] = mn[a];
+            smx[w][a] = mx[a];
+        }
+        sbad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x / kWave;
+        for (int a = 0; a < n_amb; ++a) {
+            double lo = smn[0][a], hi = smx[0][a];
+            for (int k = 1; k < nw; ++k) {
+                lo = fmin(lo, smn[k][a]);
+                hi = fmax(hi, smx[k][a]);
+            }
+            if (lo <= hi) {
+                atomicMin(&st[c].mn[a], ord_encode(lo));
+                atomicMax(&st[c].mx[a], ord_encode(hi));
+            }
+        }
+        unsigned long long tb = 0;
+        for (int k = 0; k < nw; ++k)
+            tb += sbad[k];
+        if (tb)
+            atomicAdd(&st[c].nonfinite, tb);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void key_kernel(const T *__restrict__ pts, int n_amb,
+                                                  const CloudGrid *__restrict__ grids,
+                                                  const uint32_t *__restrict__ parts,
+                                                  uint32_t *__restrict__ counts,
+                                                  uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ slots)
+{
+    const CloudGrid g = grids[blockIdx.y];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g.row0 + t;
+        int cc[3];
+        for (int a = 0; a < 3; ++a)
+            cc[a] = cell_coord<T>(pts[i * n_amb + g.axis[a]], g.lo[a], g.inv_cell, g.dim[a]);
+        const uint32_t key = (uint32_t)g.cell0 + morton_of(parts, g, cc[0], cc[1], cc[2]);
+        keys[i] = key;
+        slots[i] = atomicAdd(&counts[key], 1u);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts, int n_amb,
+                                                      const CloudGrid *__restrict__ grids,
+                                                      const uint32_t *__restrict__ cell_start,
+                                                      const uint32_t *__restrict__ keys,
+                                                      const uint32_t *__restrict__ slots,
+                                                      Pt<T> *__restrict__ spts,
+                                                      int32_t *__restrict__ perm)
+{
+    const CloudGrid g = grids[blockIdx.y];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = g.row0 + t;
+        const uint32_t pos = cell_start[keys[i]] + slots[i];
+        Pt<T> p;
+        for (int a = 0; a < 4; ++a)
+            p.v[a] = a < n_amb ? pts[i * n_amb + a] : (T)0;
+        spts[pos] = p;
+        perm[pos] = (int32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// exclusive prefix sum of uint32 (three-phase, recursive over block totals)
+// ---------------------------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t warp_tot[kScanThreads / kWave];
+    const int l = lane_id(), w = threadIdx.x / kWave;
+    int incl = wave_incl_scan((int)v);
+    if (l == kWave - 1)
+        warp_tot[w] = (uint32_t)incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int k = 0; k < kScanThreads / kWave; ++k) {
+        if (k < w)
+            base += warp_tot[k];
+        tot += warp_tot[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + (uint32_t)incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const uint32_t *__restrict__ in,
+                                                                 uint32_t *__restrict__ out,
+                                                                 uint32_t *__restrict__ tile_sums,
+                                                                 int64_t n)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems], s = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t off = block_excl_scan(s, &tot);
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n)
+            out[base + k] = off;
+        off += v[k];
+    }
+    if (threadIdx.x == 0)
+        tile_sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_add_kernel(uint32_t *__restrict__ out,
+                                                                const uint32_t *__restrict__ tile_off,
+                                                                int64_t n)
+{
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    const uint32_t add = tile_off[blockIdx.x];
+    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+        if (base + k < n)
+            out[base + k] += add;
+}
+
+// out[n] receives the grand total.
+__global__ void scan_total_kernel(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, int64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0)
+        out[n] = (n > 0) ? out[n - 1] + in[n - 1] : 0u;
+}
+
+} // namespace mvgd

@@ -1,0 +1,676 @@
+// capi.hip -- the C ABI declared in include/mvgd.h: argument checks, cell-grid sizing, device
+// memory, and the launch sequence of the assembly and apply kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mvgd.h"
+#include "apply.hpp"
+#include "assemble.hpp"
+#include "bin.hpp"
+#include "common.hpp"
+
+using namespace mvgd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+mvgd_status fail(mvgd_status s, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+// Tunables of the neighbour-search grid (cell edge and initial margin relative to the
+// estimated K-th neighbour distance). MVGD_CELL_ALPHA / MVGD_MARGIN_MU override them.
+double env_double(const char *name, double dflt)
+{
+    const char *v = getenv(name);
+    if (!v || !*v)
+        return dflt;
+    char *end = nullptr;
+    double x = strtod(v, &end);
+    return (end && end != v && std::isfinite(x) && x > 0) ? x : dflt;
+}
+
+// Allocation with an optional injected failure, to exercise the clean-up paths:
+// MVGD_FAIL_ALLOC_AT="<n>[#tag]" makes the n-th device allocation (1-based) counted from the
+// first allocation that saw this exact value fail; a new value re-arms the counter.
+std::atomic<long> g_alloc_count{0};
+std::mutex g_fail_mu;
+std::string g_fail_seen;
+long g_fail_base = 0;
+
+hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s)
+{
+    *p = nullptr;
+    const long n = ++g_alloc_count;
+    const char *f = getenv("MVGD_FAIL_ALLOC_AT");
+    if (f && *f) {
+        std::lock_guard<std::mutex> lk(g_fail_mu);
+        if (g_fail_seen != f) {
+            g_fail_seen = f;
+            g_fail_base = n - 1;
+        }
+        if (atol(f) == n - g_fail_base)
+            return hipErrorOutOfMemory;
+    }
+    if (bytes == 0)
+        bytes = 16;
+    return hipMallocAsync(p, bytes, s);
+}
+
+struct ScratchList {
+    std::vector<void *> ptrs;
+    hipStream_t s = nullptr;
+    ~ScratchList()
+    {
+        for (void *p : ptrs)
+            if (p)
+                (void)hipFreeAsync(p, s);
+    }
+    template <typename P>
+    hipError_t alloc(P **p, size_t bytes)
+    {
+        void *v = nullptr;
+        hipError_t e = dev_alloc(&v, bytes, s);
+        if (e == hipSuccess)
+            ptrs.push_back(v);
+        *p = (P *)v;
+        return e;
+    }
+};
+
+int64_t next_pow2(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v)
+        p <<= 1;
+    return p;
+}
+
+int ilog2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v)
+        ++b;
+    return b;
+}
+
+mvgd_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(MVGD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return MVGD_OK;
+}
+
+bool is_device_pointer(const void *p, int device)
+{
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return false;
+    return attr.device == device;
+}
+
+} // namespace
+
+struct mvgd_matrix {
+    int device = 0;
+    int precision = 0;
+    int K = 0;
+    int n_ambient = 0;
+    uint32_t flags = 0;
+    int64_t n_total = 0;
+    int32_t n_clouds = 0;
+    int64_t ld = 0;
+    hipStream_t stream = nullptr; // stream of the last call on this handle
+    int32_t *perm = nullptr;
+    int32_t *ell_col = nullptr;
+    void *ell_val = nullptr;
+    CloudGrid *grids = nullptr;
+    unsigned long long *counters = nullptr;
+    double *row_h = nullptr;
+    uint8_t *row_flags = nullptr;
+    void *xs = nullptr;
+    size_t xs_bytes = 0;
+    size_t bytes = 0;
+};
+
+namespace {
+
+void release(mvgd_matrix *L)
+{
+    if (!L)
+        return;
+    void *ptrs[] = {L->perm, L->ell_col, L->ell_val, L->grids, L->counters, L->row_h, L->row_flags, L->xs};
+    for (void *p : ptrs)
+        if (p)
+            (void)hipFreeAsync(p, L->stream);
+    delete L;
+}
+
+struct HostGrid {
+    CloudGrid g;
+    std::vector<uint32_t> parts;
+};
+
+// Cell grid of one cloud from its bounding box: binning axes = the three largest extents; the
+// cell edge follows the estimated K-th neighbour distance of a surface sample.
+void plan_grid(const double *mn, const double *mx, int n_amb, int64_t n, int K, int64_t row0,
+               HostGrid &hg)
+{
+    const double alpha = env_double("MVGD_CELL_ALPHA", 0.6);
+    const double mu = env_double("MVGD_MARGIN_MU", 1.5);
+    double E[4];
+    int ax[4] = {0, 1, 2, 3};
+    for (int a = 0; a < n_amb; ++a)
+        E[a] = mx[a] - mn[a];
+    std::stable_sort(ax, ax + n_amb, [&](int x, int y) { return E[x] > E[y]; });
+    double Eb[3], diam2 = 0.0;
+    for (int a = 0; a < n_amb; ++a)
+        diam2 += E[a] * E[a];
+    for (int a = 0; a < 3; ++a)
+        Eb[a] = E[ax[a]];
+    const double emax = std::max(Eb[0], 1e-300);
+    double Ef[3];
+    for (int a = 0; a < 3; ++a)
+        Ef[a] = std::max(Eb[a], emax * 1e-3);
+    const double area = 0.55 * 2.0 * (Ef[0] * Ef[1] + Ef[1] * Ef[2] + Ef[0] * Ef[2]);
+    const double rho = (double)n / area;
+    const double dk = std::sqrt((double)K / (M_PI * rho));
+    double cell = alpha * dk;
+    const int64_t cap = std::max<int64_t>(4096, next_pow2(4 * n));
+    int64_t dim[3];
+    for (int it = 0; it < 400; ++it) {
+        int64_t total = 1;
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            double cnt = std::floor(Eb[a] / cell) + 1.0;
+            if (!(cnt <= 1024.0)) {
+                ok = false;
+                cnt = 1024.0;
+            }
+            dim[a] = next_pow2((int64_t)cnt);
+            total *= dim[a];
+        }
+        if (ok && total <= cap)
+            break;
+        cell *= 1.26;
+    }
+    CloudGrid &g = hg.g;
+    memset(&g, 0, sizeof g);
+    g.row0 = row0;
+    g.n = n;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = mn[ax[a]];
+        g.dim[a] = (int32_t)dim[a];
+        g.axis[a] = ax[a];
+    }
+    g.cell = cell;
+    g.inv_cell = 1.0 / cell;
+    g.diam2 = diam2;
+    g.m0 = (int32_t)std::min(64.0, std::max(1.0, std::ceil(mu * dk / cell)));
+    // Morton part tables: bit l of the coordinate along axis a goes to its interleaved position.
+    int bits[3], maxb = 0;
+    for (int a = 0; a < 3; ++a) {
+        bits[a] = ilog2(dim[a]);
+        maxb = std::max(maxb, bits[a]);
+    }
+    int pos[3][16];
+    int p = 0;
+    for (int l = 0; l < maxb; ++l)
+        for (int a = 0; a < 3; ++a)
+            if (l < bits[a])
+                pos[a][l] = p++;
+    hg.parts.assign(dim[0] + dim[1] + dim[2], 0u);
+    int64_t off = 0;
+    for (int a = 0; a < 3; ++a) {
+        for (int64_t c = 0; c < dim[a]; ++c) {
+            uint32_t code = 0;
+            for (int l = 0; l < bits[a]; ++l)
+                code |= (uint32_t)((c >> l) & 1) << pos[a][l];
+            hg.parts[off + c] = code;
+        }
+        off += dim[a];
+    }
+}
+
+template <typename T>
+mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<int64_t> &offs,
+                          const mvgd_params &p, hipStream_t stream, mvgd_matrix **out)
+{
+    const int n_clouds = (int)offs.size() - 1;
+    const int n_amb = p.n_ambient;
+    const int K = p.k;
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess)
+        return fail(MVGD_EDEVICE, "no HIP device");
+    if (!is_device_pointer(points, device))
+        return fail(MVGD_EINVAL, "points is not device memory of the current device");
+
+    ScratchList tmp;
+    tmp.s = stream;
+    mvgd_matrix *L = new (std::nothrow) mvgd_matrix();
+    if (!L)
+        return fail(MVGD_ENOMEM, "host allocation failed");
+    L->device = device;
+    L->precision = p.precision;
+    L->K = K;
+    L->n_ambient = n_amb;
+    L->flags = p.flags;
+    L->n_total = n_total;
+    L->n_clouds = n_clouds;
+    L->ld = (n_total + kWave - 1) / kWave * kWave;
+    L->stream = stream;
+    struct Guard {
+        mvgd_matrix *&L;
+        ~Guard() { if (L) release(L); }
+    } guard{L};
+#define MVGD_ALLOC(dst, nbytes_, what)                                                            \
+    do {                                                                                          \
+        if (tmp.alloc(&(dst), (nbytes_)) != hipSuccess)                                           \
+            return fail(MVGD_ENOMEM, "device allocation failed (%s, %zu bytes)", what,            \
+                        (size_t)(nbytes_));                                                       \
+    } while (0)
+#define MVGD_KEEP(dst, nbytes_, what)                                                             \
+    do {                                                                                          \
+        void *v_ = nullptr;                                                                       \
+        if (dev_alloc(&v_, (nbytes_), stream) != hipSuccess)                                      \
+            return fail(MVGD_ENOMEM, "device allocation failed (%s, %zu bytes)", what,            \
+                        (size_t)(nbytes_));                                                       \
+        dst = (decltype(dst))v_;                                                                  \
+        L->bytes += (nbytes_);                                                                    \
+    } while (0)
+
+    // ---- 1. per-cloud bounding box and finiteness (the one synchronisation) -------------------
+    int64_t *d_offs = nullptr;
+    CloudStats *d_stats = nullptr;
+    MVGD_ALLOC(d_offs, sizeof(int64_t) * offs.size(), "offsets");
+    MVGD_ALLOC(d_stats, sizeof(CloudStats) * n_clouds, "stats");
+    if (hipMemcpyAsync(d_offs, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice,
+                       stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "copy of cloud offsets failed");
+    stats_init_kernel<<<(n_clouds + 255) / 256, 256, 0, stream>>>(d_stats, n_clouds);
+    {
+        int64_t max_n = 0;
+        for (int c = 0; c < n_clouds; ++c)
+            max_n = std::max(max_n, offs[c + 1] - offs[c]);
+        const int bx = (int)std::min<int64_t>(1024, (max_n + 255) / 256);
+        bbox_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, d_offs, d_stats);
+    }
+    if (mvgd_status st = check_launch("bbox"); st != MVGD_OK)
+        return st;
+    std::vector<CloudStats> hs(n_clouds);
+    if (hipMemcpyAsync(hs.data(), d_stats, sizeof(CloudStats) * n_clouds, hipMemcpyDeviceToHost,
+                       stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "reading the bounding boxes failed: %s",
+                    hipGetErrorString(hipGetLastError()));
+    auto decode = [](unsigned long long u) {
+        unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+        double d;
+        memcpy(&d, &b, sizeof d);
+        return d;
+    };
+    // ---- 2. grids -------------------------------------------------------------------------------
+    std::vector<HostGrid> hg(n_clouds);
+    std::vector<uint32_t> parts;
+    int64_t cell_total = 0, group_total = 0;
+    for (int c = 0; c < n_clouds; ++c) {
+        if (hs[c].nonfinite)
+            return fail(MVGD_EINVAL, "cloud %d has %llu non-finite coordinates", c,
+                        (unsigned long long)hs[c].nonfinite);
+        double mn[4], mx[4];
+        for (int a = 0; a < n_amb; ++a) {
+            mn[a] = decode(hs[c].mn[a]);
+            mx[a] = decode(hs[c].mx[a]);
+        }
+        const int64_t n = offs[c + 1] - offs[c];
+        plan_grid(mn, mx, n_amb, n, K, offs[c], hg[c]);
+        CloudGrid &g = hg[c].g;
+        g.cell0 = cell_total;
+        g.group0 = group_total;
+        g.part0 = (int64_t)parts.size();
+        parts.insert(parts.end(), hg[c].parts.begin(), hg[c].parts.end());
+        cell_total += (int64_t)g.dim[0] * g.dim[1] * g.dim[2];
+        group_total += (n + kWave - 1) / kWave;
+    }
+    if (cell_total >= (int64_t)UINT32_MAX - 1)
+        return fail(MVGD_EUNSUPPORTED, "cell table too large (%lld cells)", (long long)cell_total);
+    std::vector<CloudGrid> grids(n_clouds);
+    for (int c = 0; c < n_clouds; ++c)
+        grids[c] = hg[c].g;
+
+    // ---- 3. allocations ---------------------------------------------------------------------------
+    uint32_t *d_parts, *d_counts, *d_start, *d_keys, *d_slots;
+    Pt<T> *d_spts;
+    MVGD_ALLOC(d_parts, sizeof(uint32_t) * parts.size(), "morton tables");
+    MVGD_ALLOC(d_counts, sizeof(uint32_t) * cell_total, "cell counts");
+    MVGD_ALLOC(d_start, sizeof(uint32_t) * (cell_total + 1), "cell starts");
+    MVGD_ALLOC(d_keys, sizeof(uint32_t) * n_total, "keys");
+    MVGD_ALLOC(d_slots, sizeof(uint32_t) * n_total, "slots");
+    MVGD_ALLOC(d_spts, sizeof(Pt<T>) * n_total, "sorted points");
+    // scan levels
+    std::vector<int64_t> lvl_n;
+    for (int64_t m = cell_total; m > 1; m = (m + kScanTile - 1) / kScanTile)
+        lvl_n.push_back(m);
+    if (lvl_n.empty())
+        lvl_n.push_back(std::max<int64_t>(cell_total, 1));
+    std::vector<uint32_t *> lvl_sum(lvl_n.size()), lvl_off(lvl_n.size());
+    for (size_t l = 0; l < lvl_n.size(); ++l) {
+        const int64_t tiles = (lvl_n[l] + kScanTile - 1) / kScanTile;
+        MVGD_ALLOC(lvl_sum[l], sizeof(uint32_t) * tiles, "scan sums");
+        MVGD_ALLOC(lvl_off[l], sizeof(uint32_t) * tiles, "scan offsets");
+    }
+    const size_t vsz = sizeof(T);
+    MVGD_KEEP(L->perm, sizeof(int32_t) * n_total, "permutation");
+    MVGD_KEEP(L->ell_col, sizeof(int32_t) * (size_t)(K + 1) * L->ld, "columns");
+    MVGD_KEEP(L->ell_val, vsz * (size_t)(K + 1) * L->ld, "values");
+    MVGD_KEEP(L->grids, sizeof(CloudGrid) * n_clouds, "grids");
+    MVGD_KEEP(L->counters, sizeof(unsigned long long) * 4, "counters");
+    if (p.flags & MVGD_FLAG_KEEP_DIAG) {
+        MVGD_KEEP(L->row_h, sizeof(double) * n_total, "row h");
+        MVGD_KEEP(L->row_flags, n_total, "row flags");
+    }
+
+    // ---- 4. binning: keys, counting sort -------------------------------------------------------
+    if (hipMemcpyAsync(d_parts, parts.data(), sizeof(uint32_t) * parts.size(),
+                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(L->grids, grids.data(), sizeof(CloudGrid) * n_clouds,
+                       hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemsetAsync(d_counts, 0, sizeof(uint32_t) * cell_total, stream) != hipSuccess ||
+        hipMemsetAsync(L->counters, 0, sizeof(unsigned long long) * 4, stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "grid upload failed");
+    int64_t max_n = 0;
+    for (int c = 0; c < n_clouds; ++c)
+        max_n = std::max(max_n, offs[c + 1] - offs[c]);
+    const int bx = (int)std::min<int64_t>(2048, (max_n + 255) / 256);
+    key_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_parts,
+                                                           d_counts, d_keys, d_slots);
+    // exclusive scan of the counts, level by level
+    {
+        const uint32_t *in = d_counts;
+        uint32_t *o = d_start;
+        for (size_t l = 0; l < lvl_n.size(); ++l) {
+            const int64_t tiles = (lvl_n[l] + kScanTile - 1) / kScanTile;
+            scan_tile_kernel<<<(unsigned)tiles, kScanThreads, 0, stream>>>(in, o, lvl_sum[l], lvl_n[l]);
+            in = lvl_sum[l];
+            o = lvl_off[l];
+        }
+        for (size_t l = lvl_n.size(); l-- > 1;) {
+            const int64_t tiles = (lvl_n[l - 1] + kScanTile - 1) / kScanTile;
+            (void)tiles;
+            uint32_t *dst = (l - 1 == 0) ? d_start : lvl_off[l - 2];
+            scan_add_kernel<<<(unsigned)((lvl_n[l - 1] + kScanTile - 1) / kScanTile), kScanThreads,
+                              0, stream>>>(dst, lvl_off[l - 1], lvl_n[l - 1]);
+        }
+        scan_total_kernel<<<1, 64, 0, stream>>>(d_counts, d_start, cell_total);
+    }
+    scatter_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_start,
+                                                               d_keys, d_slots, d_spts, L->perm);
+    if (mvgd_status st = check_launch("binning"); st != MVGD_OK)
+        return st;
+
+    // ---- 5. fused neighbour search + fit + stencil ------------------------------------------
+    AsmParams ap;
+    memset(&ap, 0, sizeof ap);
+    ap.spts = d_spts;
+    ap.perm = L->perm;
+    ap.cell_start = d_start;
+    ap.parts = d_parts;
+    ap.grids = L->grids;
+    ap.n_clouds = n_clouds;
+    ap.K = K;
+    ap.n_groups = group_total;
+    ap.groups_per_xcd = (group_total + 7) / 8;
+    ap.variant = (p.flags & MVGD_FLAG_LS) ? 1 : 0;
+    ap.use_h = (p.flags & MVGD_FLAG_H_OVERRIDE) ? 1 : 0;
+    ap.h_override = p.h_override;
+    ap.ld = L->ld;
+    ap.ell_col = L->ell_col;
+    ap.ell_val = L->ell_val;
+    ap.row_h = L->row_h;
+    ap.row_flags = L->row_flags;
+    ap.counters = L->counters;
+    const size_t lds = (size_t)lds_bytes(K, (int)sizeof(Pt<T>));
+    const unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
+    if (n_amb == 3)
+        assemble_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
+    else
+        assemble_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
+    if (mvgd_status st = check_launch("assemble"); st != MVGD_OK)
+        return st;
+#undef MVGD_ALLOC
+#undef MVGD_KEEP
+    *out = L;
+    L = nullptr; // ownership passes to the caller; scratch is freed stream-ordered
+    return MVGD_OK;
+}
+
+mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_offsets,
+                     int32_t n_clouds, const mvgd_params *p, mvgd_matrix **out,
+                     std::vector<int64_t> &offs)
+{
+    if (!out)
+        return fail(MVGD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!points || !p)
+        return fail(MVGD_EINVAL, "points or params is NULL");
+    if (p->d_manifold == 1)
+        return fail(MVGD_EUNSUPPORTED, "curves (d = 1) are not implemented on the GPU path");
+    if (p->d_manifold != 2)
+        return fail(MVGD_EINVAL, "d_manifold must be 2");
+    if (p->n_ambient != 3 && p->n_ambient != 4)
+        return fail(MVGD_EINVAL, "n_ambient must be 3 or 4 (got %d)", p->n_ambient);
+    if (p->k < 5 || p->k > kMaxK)
+        return fail(MVGD_EINVAL, "k must be in [5, %d] (got %d)", kMaxK, p->k);
+    if (p->precision != MVGD_FP64 && p->precision != MVGD_FP32_MIXED)
+        return fail(MVGD_EINVAL, "unknown precision %d", p->precision);
+    if (p->flags & ~(uint32_t)(MVGD_FLAG_LS | MVGD_FLAG_H_OVERRIDE | MVGD_FLAG_KEEP_DIAG))
+        return fail(MVGD_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if ((p->flags & MVGD_FLAG_H_OVERRIDE) && !(p->h_override > 0.0 && std::isfinite(p->h_override)))
+        return fail(MVGD_EINVAL, "h_override must be positive and finite");
+    if (n_total <= 0 || n_total >= (int64_t(1) << 31))
+        return fail(MVGD_EINVAL, "n_total must be in [1, 2^31)");
+    if (cloud_offsets) {
+        if (n_clouds < 1 || n_clouds > 65535)
+            return fail(MVGD_EINVAL, "n_clouds must be in [1, 65535]");
+        offs.assign(cloud_offsets, cloud_offsets + n_clouds + 1);
+    } else {
+        offs = {0, n_total};
+    }
+    if (offs.front() != 0 || offs.back() != n_total)
+        return fail(MVGD_EINVAL, "cloud offsets must start at 0 and end at n_total");
+    for (size_t c = 0; c + 1 < offs.size(); ++c)
+        if (offs[c + 1] - offs[c] < (int64_t)p->k + 1)
+            return fail(MVGD_EINVAL, "cloud %zu has %lld points; needs more than k = %d", c,
+                        (long long)(offs[c + 1] - offs[c]), p->k);
+    return MVGD_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+mvgd_status mvgd_assemble(const void *points, int64_t n_total, const int64_t *cloud_offsets,
+                          int32_t n_clouds, const mvgd_params *p, void *stream, mvgd_matrix **out)
+{
+    std::vector<int64_t> offs;
+    mvgd_status st = validate(points, n_total, cloud_offsets, n_clouds, p, out, offs);
+    if (st != MVGD_OK)
+        return st;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        return fail(MVGD_EDEVICE, "no HIP device available");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (p->precision == MVGD_FP64)
+        return assemble_impl<double>((const double *)points, n_total, offs, *p, s, out);
+    return assemble_impl<float>((const float *)points, n_total, offs, *p, s, out);
+}
+
+mvgd_status mvgd_apply(mvgd_matrix *L, const void *x, void *y, int32_t nrhs, void *stream)
+{
+    if (!L || !x || !y)
+        return fail(MVGD_EINVAL, "NULL argument");
+    if (nrhs < 1 || nrhs > 64)
+        return fail(MVGD_EINVAL, "nrhs must be in [1, 64]");
+    hipStream_t s = (hipStream_t)stream;
+    if (!is_device_pointer(x, L->device) || !is_device_pointer(y, L->device))
+        return fail(MVGD_EINVAL, "x and y must be device memory of the matrix's device");
+    const size_t vsz = L->precision == MVGD_FP64 ? 8 : 4;
+    const size_t need = vsz * (size_t)L->n_total * nrhs;
+    {
+        const char *xb = (const char *)x, *yb = (const char *)y;
+        if (xb < yb + need && yb < xb + need)
+            return fail(MVGD_EINVAL, "x and y overlap");
+    }
+    if (L->xs_bytes < need) {
+        if (L->xs)
+            (void)hipFreeAsync(L->xs, L->stream);
+        L->xs = nullptr;
+        L->xs_bytes = 0;
+        void *v = nullptr;
+        if (dev_alloc(&v, need, s) != hipSuccess)
+            return fail(MVGD_ENOMEM, "apply staging allocation failed (%zu bytes)", need);
+        L->xs = v;
+        L->xs_bytes = need;
+    }
+    L->stream = s;
+    const int64_t n = L->n_total;
+    const int slots = L->K + 1;
+    const int64_t nt = n * nrhs;
+    const unsigned gb = (unsigned)((nt + 255) / 256), rb = (unsigned)((n + 255) / 256);
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        const T *xx = (const T *)x;
+        T *xs = (T *)L->xs, *yy = (T *)y;
+        const T *val = (const T *)L->ell_val;
+        gather_rows_kernel<T><<<gb, 256, 0, s>>>(xx, L->perm, xs, n, nrhs);
+        switch (nrhs) {
+        case 1: spmv_ell_kernel<T, 1><<<rb, 256, 0, s>>>(L->ell_col, val, xs, L->perm, yy, n, L->ld, slots); break;
+        case 2: spmv_ell_kernel<T, 2><<<rb, 256, 0, s>>>(L->ell_col, val, xs, L->perm, yy, n, L->ld, slots); break;
+        case 4: spmv_ell_kernel<T, 4><<<rb, 256, 0, s>>>(L->ell_col, val, xs, L->perm, yy, n, L->ld, slots); break;
+        case 8: spmv_ell_kernel<T, 8><<<rb, 256, 0, s>>>(L->ell_col, val, xs, L->perm, yy, n, L->ld, slots); break;
+        default:
+            spmv_ell_any_kernel<T><<<gb, 256, 0, s>>>(L->ell_col, val, xs, L->perm, yy, n, L->ld, slots, nrhs);
+        }
+    };
+    if (L->precision == MVGD_FP64)
+        run(double());
+    else
+        run(float());
+    return check_launch("apply");
+}
+
+void mvgd_free(mvgd_matrix *L)
+{
+    release(L);
+}
+
+mvgd_status mvgd_csr(mvgd_matrix *L, int64_t *row_ptr, int32_t *col, void *val, void *stream)
+{
+    if (!L)
+        return fail(MVGD_EINVAL, "NULL matrix");
+    hipStream_t s = (hipStream_t)stream;
+    if ((row_ptr && !is_device_pointer(row_ptr, L->device)) ||
+        (col && !is_device_pointer(col, L->device)) || (val && !is_device_pointer(val, L->device)))
+        return fail(MVGD_EINVAL, "CSR buffers must be device memory of the matrix's device");
+    L->stream = s;
+    const int64_t n = L->n_total;
+    const unsigned nb = (unsigned)((n + 63) / 64);
+    if (L->precision == MVGD_FP64)
+        export_csr_kernel<double><<<nb, 64, 0, s>>>(L->ell_col, (const double *)L->ell_val, L->perm,
+                                                    L->grids, L->n_clouds, n, L->ld, L->K + 1,
+                                                    row_ptr, col, (double *)val);
+    else
+        export_csr_kernel<float><<<nb, 64, 0, s>>>(L->ell_col, (const float *)L->ell_val, L->perm,
+                                                   L->grids, L->n_clouds, n, L->ld, L->K + 1,
+                                                   row_ptr, col, (float *)val);
+    return check_launch("csr export");
+}
+
+mvgd_status mvgd_row_diag(mvgd_matrix *L, double *h, uint8_t *status, void *stream)
+{
+    if (!L)
+        return fail(MVGD_EINVAL, "NULL matrix");
+    if (!L->row_h)
+        return fail(MVGD_EINVAL, "the matrix was assembled without MVGD_FLAG_KEEP_DIAG");
+    if ((h && !is_device_pointer(h, L->device)) || (status && !is_device_pointer(status, L->device)))
+        return fail(MVGD_EINVAL, "diagnostic buffers must be device memory of the matrix's device");
+    hipStream_t s = (hipStream_t)stream;
+    L->stream = s;
+    const int64_t n = L->n_total;
+    diag_scatter_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(L->row_h, L->row_flags, L->perm,
+                                                                   h, status, n);
+    return check_launch("row diagnostics");
+}
+
+mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info)
+{
+    if (!L || !info)
+        return fail(MVGD_EINVAL, "NULL argument");
+    unsigned long long c[4] = {0, 0, 0, 0};
+    if (hipMemcpyAsync(c, L->counters, sizeof c, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
+        hipStreamSynchronize(L->stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "reading counters failed");
+    if (c[2])
+        return fail(MVGD_EDEVICE, "internal consistency check failed on %llu rows", c[2]);
+    memset(info, 0, sizeof *info);
+    info->n_rows = L->n_total;
+    info->n_clouds = L->n_clouds;
+    info->k = L->K;
+    info->nnz = L->n_total * (L->K + 1);
+    info->precision = L->precision;
+    info->n_ambient = L->n_ambient;
+    info->n_degenerate = (int64_t)c[0];
+    info->n_slow_knn = (int64_t)c[1];
+    info->device_bytes = L->bytes + L->xs_bytes;
+    return MVGD_OK;
+}
+
+const char *mvgd_status_str(mvgd_status s)
+{
+    switch (s) {
+    case MVGD_OK: return "MVGD_OK";
+    case MVGD_EINVAL: return "MVGD_EINVAL";
+    case MVGD_ENOMEM: return "MVGD_ENOMEM";
+    case MVGD_EDEVICE: return "MVGD_EDEVICE";
+    case MVGD_EUNSUPPORTED: return "MVGD_EUNSUPPORTED";
+    }
+    return "MVGD_UNKNOWN";
+}
+
+const char *mvgd_last_error(void)
+{
+    return g_err;
+}
+
+int32_t mvgd_version(void)
+{
+    return 100; // 0.1.0
+}
+
+} // extern "C"

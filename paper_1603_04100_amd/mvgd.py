@@ -1,0 +1,189 @@
+"""ctypes binding of the MVGD C ABI (include/mvgd.h).
+
+Argument marshalling only: torch tensors provide device memory and the current stream; every
+step of assembly and apply runs in the HIP kernels of ``libmvgd.so``. There is no CPU fallback:
+importing this module fails loudly when the library has not been built.
+
+    L = mvgd_assemble(points, k=32, precision="fp32")   # points: [N, n] cuda tensor
+    y = mvgd_apply(L, x)                                 # x: [N] or [N, R]
+    row_ptr, col, val = mvgd_csr(L)
+    mvgd_free(L)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmvgd.so")
+
+MVGD_OK, MVGD_EINVAL, MVGD_ENOMEM, MVGD_EDEVICE, MVGD_EUNSUPPORTED = 0, -1, -2, -3, -4
+MVGD_FP64, MVGD_FP32_MIXED = 0, 1
+MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG = 1, 2, 4
+
+EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
+           "mvgd_status_str", "mvgd_last_error", "mvgd_version")
+
+
+class MvgdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+class mvgd_params(ctypes.Structure):
+    _fields_ = [("n_ambient", ctypes.c_int32), ("d_manifold", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("h_override", ctypes.c_double)]
+
+
+class mvgd_info_t(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_clouds", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("nnz", ctypes.c_int64), ("precision", ctypes.c_int32),
+                ("n_ambient", ctypes.c_int32), ("n_degenerate", ctypes.c_int64),
+                ("n_slow_knn", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"MVGD HIP library not built: {path} is missing "
+                          "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.mvgd_assemble.argtypes = [vp, i64, vp, i32, ctypes.POINTER(mvgd_params), vp,
+                                  ctypes.POINTER(vp)]
+    lib.mvgd_assemble.restype = i32
+    lib.mvgd_apply.argtypes = [vp, vp, vp, i32, vp]
+    lib.mvgd_apply.restype = i32
+    lib.mvgd_free.argtypes = [vp]
+    lib.mvgd_free.restype = None
+    lib.mvgd_csr.argtypes = [vp, vp, vp, vp, vp]
+    lib.mvgd_csr.restype = i32
+    lib.mvgd_row_diag.argtypes = [vp, vp, vp, vp]
+    lib.mvgd_row_diag.restype = i32
+    lib.mvgd_info.argtypes = [vp, ctypes.POINTER(mvgd_info_t)]
+    lib.mvgd_info.restype = i32
+    lib.mvgd_status_str.argtypes = [i32]
+    lib.mvgd_status_str.restype = ctypes.c_char_p
+    lib.mvgd_last_error.argtypes = []
+    lib.mvgd_last_error.restype = ctypes.c_char_p
+    lib.mvgd_version.argtypes = []
+    lib.mvgd_version.restype = i32
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(status: int):
+    if status != MVGD_OK:
+        raise MvgdError(status, f"{_lib.mvgd_status_str(status).decode()}: "
+                                f"{_lib.mvgd_last_error().decode()}")
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Matrix:
+    """Handle of an assembled MVGD matrix (owns its device memory until ``free``)."""
+
+    def __init__(self, handle: int, n_rows: int, k: int, dtype: torch.dtype, device):
+        self._h = ctypes.c_void_p(handle)
+        self.n_rows, self.k, self.dtype, self.device = n_rows, k, dtype, device
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("matrix already freed")
+        return self._h
+
+    def free(self):
+        if self._h:
+            _lib.mvgd_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision=None,
+                  flags: int = 0, h_override: float | None = None, d_manifold: int = 2,
+                  stream=None) -> Matrix:
+    """Assemble L from device points [N, n] (float32 -> FP32-mixed, float64 -> FP64)."""
+    if not isinstance(points, torch.Tensor) or points.dim() != 2:
+        raise ValueError("points must be a 2-D torch tensor")
+    if precision is None:
+        precision = "fp64" if points.dtype == torch.float64 else "fp32"
+    prec = {"fp64": MVGD_FP64, "fp32": MVGD_FP32_MIXED}[precision]
+    want = torch.float64 if prec == MVGD_FP64 else torch.float32
+    if points.dtype != want:
+        raise ValueError(f"points dtype {points.dtype} does not match precision {precision}")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous")
+    if h_override is not None:
+        flags |= MVGD_FLAG_H_OVERRIDE
+    p = mvgd_params(points.shape[1], d_manifold, k, prec, flags, float(h_override or 0.0))
+    offs_ptr, n_clouds = None, 1
+    if cloud_offsets is not None:
+        offs = (ctypes.c_int64 * len(cloud_offsets))(*[int(v) for v in cloud_offsets])
+        offs_ptr, n_clouds = ctypes.cast(offs, ctypes.c_void_p), len(cloud_offsets) - 1
+    out = ctypes.c_void_p()
+    _check(_lib.mvgd_assemble(ctypes.c_void_p(points.data_ptr()), points.shape[0], offs_ptr,
+                              n_clouds, ctypes.byref(p), ctypes.c_void_p(_stream(stream)),
+                              ctypes.byref(out)))
+    return Matrix(out.value, points.shape[0], k, want, points.device)
+
+
+def mvgd_apply(L: Matrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+    """y = L x for x [N] or [N, R] (matrix dtype, contiguous, on the matrix's device)."""
+    squeeze = x.dim() == 1
+    x2 = x.reshape(x.shape[0], -1)
+    if x2.dtype != L.dtype or not x2.is_contiguous() or x2.shape[0] != L.n_rows:
+        raise ValueError("x must be a contiguous tensor of the matrix dtype with n_rows rows")
+    if y is None:
+        y = torch.empty_like(x2)
+    _check(_lib.mvgd_apply(L.handle, ctypes.c_void_p(x2.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                           x2.shape[1], ctypes.c_void_p(_stream(stream))))
+    return y.reshape(-1) if squeeze else y
+
+
+def mvgd_free(L: Matrix):
+    L.free()
+
+
+def mvgd_csr(L: Matrix, stream=None):
+    """CSR in the caller's point order: (row_ptr int64 [N+1], col int32 [nnz], val [nnz])."""
+    nnz = L.n_rows * (L.k + 1)
+    row_ptr = torch.empty(L.n_rows + 1, dtype=torch.int64, device=L.device)
+    col = torch.empty(nnz, dtype=torch.int32, device=L.device)
+    val = torch.empty(nnz, dtype=L.dtype, device=L.device)
+    _check(_lib.mvgd_csr(L.handle, ctypes.c_void_p(row_ptr.data_ptr()),
+                         ctypes.c_void_p(col.data_ptr()), ctypes.c_void_p(val.data_ptr()),
+                         ctypes.c_void_p(_stream(stream))))
+    return row_ptr, col, val
+
+
+def mvgd_row_diag(L: Matrix, stream=None):
+    """Per-row spacing h (float64) and status bits (uint8); needs MVGD_FLAG_KEEP_DIAG."""
+    h = torch.empty(L.n_rows, dtype=torch.float64, device=L.device)
+    st = torch.empty(L.n_rows, dtype=torch.uint8, device=L.device)
+    _check(_lib.mvgd_row_diag(L.handle, ctypes.c_void_p(h.data_ptr()),
+                              ctypes.c_void_p(st.data_ptr()), ctypes.c_void_p(_stream(stream))))
+    return h, st
+
+
+def mvgd_info(L: Matrix) -> dict:
+    info = mvgd_info_t()
+    _check(_lib.mvgd_info(L.handle, ctypes.byref(info)))
+    return {name: getattr(info, name) for name, _ in mvgd_info_t._fields_}
+
+
+def version() -> int:
+    return int(_lib.mvgd_version())

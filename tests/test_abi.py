@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every symbol include/mvgd.h declares, and rejects invalid
+arguments on the host before touching a device (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mvgd.h")
+LIB = os.path.join(ROOT, "paper_1603_04100_amd", "libmvgd.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mvgd_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def mv():
+    from paper_1603_04100_amd import mvgd
+    return mvgd
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_info"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(mv):
+    lib = ctypes.CDLL(LIB)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mvgd_\w+)", out))
+    assert set(_declared()) <= exported
+    assert set(mv.EXPORTS) == set(_declared())
+
+
+def test_status_strings_and_version(mv):
+    lib = mv._lib
+    assert lib.mvgd_status_str(0) == b"MVGD_OK"
+    assert lib.mvgd_status_str(-1) == b"MVGD_EINVAL"
+    assert lib.mvgd_status_str(-4) == b"MVGD_EUNSUPPORTED"
+    assert lib.mvgd_version() >= 100
+
+
+def _call(mv, params, n_total=1000, offsets=None, n_clouds=1, points=0x1000, out=True):
+    lib = mv._lib
+    o = ctypes.c_void_p()
+    offs = None
+    if offsets is not None:
+        arr = (ctypes.c_int64 * len(offsets))(*offsets)
+        offs = ctypes.cast(arr, ctypes.c_void_p)
+    st = lib.mvgd_assemble(ctypes.c_void_p(points), n_total, offs, n_clouds,
+                           ctypes.byref(params) if params is not None else None, None,
+                           ctypes.byref(o) if out else None)
+    return st, o.value
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("k", 4, -1), ("k", 64, -1), ("n_ambient", 2, -1), ("n_ambient", 5, -1),
+    ("d_manifold", 3, -1), ("d_manifold", 1, -4), ("precision", 7, -1), ("flags", 1 << 9, -1),
+])
+def test_invalid_parameters_rejected_on_host(mv, field, value, status):
+    p = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, 0, 0.0)
+    setattr(p, field, value)
+    st, h = _call(mv, p)
+    assert st == status and h is None
+    assert mv._lib.mvgd_last_error()
+
+
+def test_invalid_shapes_rejected_on_host(mv):
+    p = mv.mvgd_params(3, 2, 20, mv.MVGD_FP32_MIXED, 0, 0.0)
+    assert _call(mv, None)[0] == -1
+    assert _call(mv, p, points=0)[0] == -1
+    assert _call(mv, p, out=False)[0] == -1
+    assert _call(mv, p, n_total=0)[0] == -1
+    assert _call(mv, p, n_total=20)[0] == -1                      # needs more than k points
+    assert _call(mv, p, offsets=[0, 500, 900], n_clouds=2)[0] == -1  # does not end at n_total
+    assert _call(mv, p, offsets=[0, 990, 1000], n_clouds=2)[0] == -1  # second cloud too small
+    assert _call(mv, p, offsets=[1, 500, 1000], n_clouds=2)[0] == -1
+    q = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, mv.MVGD_FLAG_H_OVERRIDE, -1.0)
+    assert _call(mv, q)[0] == -1
+
+
+def test_apply_and_free_accept_null_safely(mv):
+    lib = mv._lib
+    assert lib.mvgd_apply(None, None, None, 1, None) == -1
+    assert lib.mvgd_csr(None, None, None, None, None) == -1
+    lib.mvgd_free(None)

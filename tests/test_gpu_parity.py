@@ -1,0 +1,307 @@
+"""GPU path (HIP, through the C ABI) against the FP64 oracle, element by element.
+
+Bars (the targets of the build):
+* kNN sets and CSR sparsity: bit-exact (columns identical).
+* FP64 mode: row-relative error max_j |L_gpu - L_oracle| / max_j |L_oracle| <= 1e-12.
+  Exception derived from the arithmetic: the in-plane PCA axes fix h, and rounding of the
+  covariance (~1e-16 relative) rotates them by ~1e-16/gap, gap = (lam1 - lam2)/lam1; so rows
+  get tol = max(1e-12, 4e-15 / gap). Rows with gap < 4e-3 are the only ones it widens.
+* FP32-mixed mode: the oracle runs on the same FP32-rounded coordinates; rows <= 1e-4.
+* Apply: y = L x against the exported CSR times x in FP64 (accumulation in double on the GPU).
+Every case prints its L.f error against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1603_04100_amd import clouds
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def mv():
+    from paper_1603_04100_amd import mvgd
+    return mvgd
+
+
+def _gpu_csr(mv, pts, k, precision, offsets=None, **kw):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    P = torch.tensor(pts, dtype=dt, device=DEV)
+    L = mv.mvgd_assemble(P, k, precision=precision, cloud_offsets=offsets, **kw)
+    rp, col, val = mv.mvgd_csr(L)
+    info = mv.mvgd_info(L)
+    torch.cuda.synchronize()
+    return L, P, rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy().astype(np.float64), info
+
+
+def _oracle_points(pts, precision):
+    return pts.astype(np.float32).astype(np.float64) if precision == "fp32" else pts
+
+
+def _row_tol(precision, gap):
+    if precision == "fp32":
+        return np.full(gap.shape, 1e-4)
+    return np.maximum(1e-12, 4e-15 / np.maximum(gap, 1e-300))
+
+
+def _compare_rows(g_cols, g_vals, o_cols, o_vals, tol):
+    assert (g_cols == o_cols).all(), "kNN / sparsity differ"
+    scale = np.abs(o_vals).max(1)
+    err = np.abs(g_vals - o_vals).max(1)
+    zero = scale == 0
+    assert (err[zero] == 0).all(), "degenerate rows must be zero on both sides"
+    rel = np.where(zero, 0.0, err / np.where(zero, 1.0, scale))
+    bad = np.nonzero(rel > tol)[0]
+    assert bad.size == 0, f"{bad.size} rows over tolerance, worst {rel.max():.3e} at {bad[:5]}"
+    return rel
+
+
+def _lf_error(mv, L, P, f, o_rp, o_cols, o_vals, precision):
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    y = mv.mvgd_apply(L, torch.tensor(f, dtype=dt, device=DEV)).cpu().numpy().astype(np.float64)
+    ref = oracle.apply(o_rp, o_cols, o_vals, f)
+    return np.abs(y - ref).max() / np.abs(ref).max(), y
+
+
+def _full_case(mv, cl, precision, **kw):
+    pts = cl.points
+    k = cl.k
+    n = pts.shape[0]
+    L, P, rp, col, val, info = _gpu_csr(mv, pts, k, precision, **kw)
+    opts = _oracle_points(pts, precision)
+    o_cols, o_vals, dg = oracle.rows(opts, k, diag=True,
+                                     variant="ls" if kw.get("flags", 0) & 1 else "mvgd")
+    gap = (dg[:, 2] - dg[:, 3]) / dg[:, 2]
+    rel = _compare_rows(col.reshape(n, k + 1), val.reshape(n, k + 1), o_cols, o_vals,
+                        _row_tol(precision, gap))
+    assert (rp == np.arange(n + 1) * (k + 1)).all()
+    o_rp = np.arange(n + 1, dtype=np.int64) * (k + 1)
+    lf, y = _lf_error(mv, L, P, cl.f[:, 0], o_rp, o_cols.reshape(-1), o_vals.reshape(-1), precision)
+    print(f"\n[{cl.name} N={n} K={k} {precision}] max row rel err {rel.max():.2e}, "
+          f"L.f rel err vs FP64 oracle {lf:.2e}, max|Lf - Delta f| {np.abs(y - cl.lap_f[:, 0]).max():.3e}, "
+          f"degenerate {info['n_degenerate']}, slow-knn {info['n_slow_knn']}")
+    return L, P, col, val, rel, lf, info
+
+
+# ----------------------------------------------------------------------------------------------
+# whole matrices at sizes the oracle finishes in seconds (several tiles and a ragged tail)
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_sphere_2k(mv, precision):
+    cl = clouds.sphere(2000, 1, 20)
+    L, P, col, val, rel, lf, info = _full_case(mv, cl, precision)
+    v = val.reshape(2000, 21)
+    assert np.all(np.abs(v.sum(1)) <= (1e-12 if precision == "fp64" else 1e-5) * np.abs(v).sum(1))
+    assert info["n_degenerate"] == 0
+    L.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_torus_nonuniform(mv, precision):
+    cl = clouds.torus(20_037, 2, 24)
+    L, *_ = _full_case(mv, cl, precision)
+    L.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_flat_torus_r4(mv, precision):
+    cl = clouds.flat_torus4(30_001, 4, 32)
+    L, *_ = _full_case(mv, cl, precision)
+    L.free()
+
+
+@pytest.mark.parametrize("k", [5, 12, 63])
+def test_k_range_and_tiny_clouds(mv, k):
+    cl = clouds.sphere(k + 1 + 70, 9, k)
+    L, *_ = _full_case(mv, cl, "fp64")
+    L.free()
+    cl = clouds.sphere(k + 1, 10, k)  # minimal cloud: every other point is a neighbour
+    L, *_ = _full_case(mv, cl, "fp64")
+    L.free()
+
+
+def test_ls_variant_and_h_override(mv):
+    cl = clouds.sphere(3000, 17, 20)
+    L, *_ = _full_case(mv, cl, "fp64", flags=mv.MVGD_FLAG_LS)
+    L.free()
+    pts = cl.points
+    P = torch.tensor(pts, device=DEV)
+    L = mv.mvgd_assemble(P, 20, h_override=0.05)
+    rp, col, val = mv.mvgd_csr(L)
+    oc, ov = oracle.rows(pts, 20, h_override=0.05)
+    _compare_rows(col.cpu().numpy().reshape(-1, 21), val.cpu().numpy().reshape(-1, 21), oc, ov,
+                  np.full(3000, 1e-12))
+    L.free()
+
+
+def test_exact_ties_on_a_lattice(mv):
+    """Planar lattice: many equal distances; the tie-break (smaller index) must match."""
+    g = np.stack(np.meshgrid(np.arange(40), np.arange(30), indexing="ij"), -1).reshape(-1, 2)
+    pts = np.concatenate([g * 0.5, np.zeros((g.shape[0], 1))], 1).astype(np.float64)
+    pts = pts @ np.linalg.qr(np.random.default_rng(1).standard_normal((3, 3)))[0].T
+    perm = np.random.default_rng(2).permutation(pts.shape[0])
+    pts = np.ascontiguousarray(pts[perm])
+    for precision in ("fp64", "fp32"):
+        L, P, rp, col, val, info = _gpu_csr(mv, pts, 12, precision)
+        oc, ov = oracle.rows(_oracle_points(pts, precision), 12)
+        assert (col.reshape(-1, 13) == oc).all()
+        L.free()
+
+
+def test_duplicates_and_degenerate(mv):
+    rng = np.random.default_rng(3)
+    base = clouds.sphere(1500, 5, 16).points
+    pts = np.concatenate([base, base[:200]])  # exact duplicates
+    pts = np.ascontiguousarray(pts[rng.permutation(pts.shape[0])])
+    L, *_ = _full_case(mv, clouds.Cloud("dups", pts, np.array([0, pts.shape[0]]), 16,
+                                        pts[:, :1].copy(), np.full((pts.shape[0], 1), np.nan)),
+                       "fp64")
+    L.free()
+    t = np.linspace(0, 1, 300)
+    line = np.ascontiguousarray(np.stack([t, 2 * t, -t], 1))
+    L, P, rp, col, val, info = _gpu_csr(mv, line, 8, "fp64")
+    oc, ov = oracle.rows(line, 8)
+    assert (col.reshape(-1, 9) == oc).all()
+    assert (val == 0).all() and info["n_degenerate"] == 300
+    L.free()
+
+
+# ----------------------------------------------------------------------------------------------
+# batched clouds: per-cloud parity, and batched == alone (bit-identical)
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_clouds(mv, precision):
+    cl = clouds.ellipsoid_batch(n_clouds=6, seed=3, k=20, n_min=400, n_max=6000)
+    pts, offs = cl.points, cl.offsets
+    L, P, rp, col, val, info = _gpu_csr(mv, pts, 20, precision, offsets=list(offs))
+    opts = _oracle_points(pts, precision)
+    for c in range(len(offs) - 1):
+        a, b = offs[c], offs[c + 1]
+        oc, ov, dg = oracle.rows(opts[a:b], 20, diag=True)
+        gap = (dg[:, 2] - dg[:, 3]) / dg[:, 2]
+        _compare_rows(col[a * 21:b * 21].reshape(-1, 21), val[a * 21:b * 21].reshape(-1, 21), oc,
+                      ov, _row_tol(precision, gap))
+        L1, P1, rp1, col1, val1, _ = _gpu_csr(mv, np.ascontiguousarray(pts[a:b]), 20, precision)
+        assert (col1 == col[a * 21:b * 21]).all()
+        assert (val1 == val[a * 21:b * 21]).all()
+        L1.free()
+    # apply with 4 right-hand sides
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    x = torch.tensor(cl.f, dtype=dt, device=DEV)
+    y = mv.mvgd_apply(L, x).cpu().numpy().astype(np.float64)
+    ref = np.stack([oracle.apply(rp, col.astype(np.int64) + np.repeat(offs[:-1], np.diff(offs) * 21),
+                                 val, cl.f[:, r].astype(np.float32 if precision == "fp32" else np.float64))
+                    for r in range(4)], 1)
+    tol = 1e-13 if precision == "fp64" else 1e-6
+    assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
+    L.free()
+
+
+# ----------------------------------------------------------------------------------------------
+# apply against the exported CSR, several right-hand-side counts
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nrhs", [1, 3, 8])
+def test_apply_matches_exported_csr(mv, precision, nrhs):
+    cl = clouds.torus(9_999, 21, 24)
+    L, P, rp, col, val, info = _gpu_csr(mv, cl.points, 24, precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    x = torch.randn(cl.points.shape[0], nrhs, dtype=dt, device=DEV)
+    y = mv.mvgd_apply(L, x).cpu().numpy().astype(np.float64)
+    ref = oracle.apply(rp, col.astype(np.int64), val, x.cpu().numpy().astype(np.float64))
+    tol = 1e-13 if precision == "fp64" else 2e-7
+    assert np.abs(y - ref).max() <= tol * np.abs(ref).max() * 10
+    L.free()
+
+
+def test_determinism(mv):
+    cl = clouds.flat_torus4(20_000, 8, 32)
+    a = _gpu_csr(mv, cl.points, 32, "fp32")
+    b = _gpu_csr(mv, cl.points, 32, "fp32")
+    assert (a[3] == b[3]).all() and (a[4] == b[4]).all()
+    a[0].free()
+    b[0].free()
+
+
+# ----------------------------------------------------------------------------------------------
+# full-size workloads, in the launch configuration the benchmark times: sampled rows
+# ----------------------------------------------------------------------------------------------
+def _sampled(mv, cl, precision, n_rows=600):
+    pts, k = cl.points, cl.k
+    n = pts.shape[0]
+    L, P, rp, col, val, info = _gpu_csr(mv, pts, k, precision)
+    rows = np.random.default_rng(0).choice(n, n_rows, replace=False)
+    oc, ov, dg = oracle.rows(_oracle_points(pts, precision), k, rows=rows, diag=True)
+    gap = (dg[:, 2] - dg[:, 3]) / dg[:, 2]
+    rel = _compare_rows(col.reshape(n, k + 1)[rows], val.reshape(n, k + 1)[rows], oc, ov,
+                        _row_tol(precision, gap))
+    v = val.reshape(n, k + 1)
+    rs = np.abs(v.sum(1)) / np.abs(v).sum(1)
+    y = mv.mvgd_apply(L, torch.tensor(cl.f[:, 0], dtype=P.dtype, device=DEV)).cpu().numpy()
+    ref = (ov * cl.f[oc, 0]).sum(1)  # oracle rows applied to f, FP64
+    lf = np.abs(ref - y[rows]).max() / np.abs(ref).max()
+    print(f"\n[{cl.name} N={n} {precision} sampled {n_rows}] max row rel err {rel.max():.2e}, "
+          f"L.f rel err (sampled rows) {lf:.2e}, max row-sum/|row| {rs.max():.1e}, "
+          f"max|Lf - Delta f| {np.abs(y - cl.lap_f[:, 0]).max():.3e}, slow-knn {info['n_slow_knn']}")
+    assert info["n_degenerate"] == 0
+    L.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_torus_200k_sampled(mv, precision):
+    _sampled(mv, clouds.torus(200_000, 2, 24), precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_flat_torus_1m_sampled(mv, precision):
+    _sampled(mv, clouds.flat_torus4(1_000_000, 4, 32), precision, n_rows=400)
+
+
+# ----------------------------------------------------------------------------------------------
+# error paths on the device
+# ----------------------------------------------------------------------------------------------
+def test_nonfinite_points_rejected(mv):
+    pts = clouds.sphere(500, 1, 10).points.copy()
+    pts[17, 2] = np.nan
+    with pytest.raises(mv.MvgdError) as e:
+        mv.mvgd_assemble(torch.tensor(pts, device=DEV), 10)
+    assert e.value.status == mv.MVGD_EINVAL
+
+
+def test_host_pointer_rejected(mv):
+    P = torch.tensor(clouds.sphere(500, 1, 10).points)  # CPU tensor
+    with pytest.raises(mv.MvgdError) as e:
+        mv.mvgd_assemble(P, 10)
+    assert e.value.status == mv.MVGD_EINVAL
+
+
+def test_allocation_failure_cleans_up(mv):
+    """Every allocation of assemble/apply can fail: the call returns ENOMEM, leaks nothing that
+    breaks later calls, and a clean call afterwards gives the same matrix."""
+    import os
+    pts = torch.tensor(clouds.sphere(3000, 1, 20).points, device=DEV)
+    ref = mv.mvgd_assemble(pts, 20)
+    rc, cc, vc = mv.mvgd_csr(ref)
+    seen = []
+    for at in range(1, 24):
+        os.environ["MVGD_FAIL_ALLOC_AT"] = f"{at}#{at}"
+        try:
+            L = mv.mvgd_assemble(pts, 20)
+            y = mv.mvgd_apply(L, pts[:, 0].contiguous())
+            seen.append(0)
+            L.free()
+        except mv.MvgdError as e:
+            assert e.status == mv.MVGD_ENOMEM, e
+            seen.append(e.status)
+        finally:
+            del os.environ["MVGD_FAIL_ALLOC_AT"]
+    assert mv.MVGD_ENOMEM in seen and seen[-1] == 0
+    L = mv.mvgd_assemble(pts, 20)
+    r2, c2, v2 = mv.mvgd_csr(L)
+    assert torch.equal(c2, cc) and torch.equal(v2, vc)
+    L.free()
+    ref.free()
