@@ -54,7 +54,9 @@ enum {
     MVGD_FLAG_LS = 1u << 0,         /* plain least-squares discretisation (Sec. 2): derivatives
                                        of the fitted quadratic at p_i, no centre modification */
     MVGD_FLAG_H_OVERRIDE = 1u << 1, /* use params.h_override as the grid spacing of every row */
-    MVGD_FLAG_KEEP_DIAG = 1u << 2   /* keep per-row h and status bits for mvgd_row_diag */
+    MVGD_FLAG_KEEP_DIAG = 1u << 2,  /* keep per-row h and status bits for mvgd_row_diag */
+    MVGD_FLAG_TIME = 1u << 3        /* record HIP events around the kernel groups of assemble
+                                       and apply on the caller's stream (see mvgd_timing) */
 };
 
 typedef struct {
@@ -149,6 +151,17 @@ mvgd_status mvgd_csr(mvgd_matrix *L, int64_t *row_ptr, int32_t *col, void *val, 
  * otherwise MVGD_EINVAL. Either pointer may be NULL. Stream-ordered.
  */
 mvgd_status mvgd_row_diag(mvgd_matrix *L, double *h, uint8_t *status, void *stream);
+
+typedef struct {
+    float bin_ms;      /* assemble: bounding box, host planning gap, cell keys, scan, scatter */
+    float assemble_ms; /* assemble: the fused neighbour-search + fit + stencil kernel */
+    float apply_ms;    /* last mvgd_apply: permutation of x + ELL SpMV */
+    int32_t have_apply;
+} mvgd_timing_t;
+
+/* mvgd_timing -- device durations measured with HIP events on the stream each call was enqueued
+ * on; needs MVGD_FLAG_TIME at assembly, otherwise MVGD_EINVAL. Waits for the handle's stream. */
+mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t);
 
 /* mvgd_info -- sizes and counters; waits for the handle's stream (synchronous). */
 mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info);

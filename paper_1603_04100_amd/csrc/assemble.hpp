@@ -24,7 +24,8 @@
 // Cholesky in FP64; fits of the normal coordinates (Eq. poly); inverse metric G and drift q
 // of the fitted graph (Eq. metric, Eq. eqn3); ell = (tau, -q1, -q2, 2G11, 2G12, 2G22),
 // tau = 2 (G11 + G22)/h^2 (centre value U_i in the virtual-grid differences, Eq. centered1);
-// y = Gram^-1 D ell with one FP64 refinement step on V^T w = D ell; w = V y, w_centre -= tau.
+// y = Gram^-1 D ell; w = V y, w_centre -= tau. In FP64 mode the surface fits and y each get one
+// refinement step whose residual is formed from V itself (accuracy O(kappa(V) u), as a QR).
 #pragma once
 
 #include "common.hpp"
@@ -715,8 +716,56 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         double g11 = 1.0, g12 = 0.0, g22 = 1.0;
         double zx[NC], zy[NC], h11[NC], h12[NC], h22[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC; ++c)
             chol6_solve(Gm, inv_d, rz[c]);
+        if (sizeof(T) == 8) {
+            // one refinement step of the surface fits, residual V^T (z - V a) formed from V
+            double res[NC][6];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    res[c][t] = 0.0;
+                res[c][0] = -rz[c][0]; // centre row e1 with z = 0
+            }
+            for (int k = 0; k < K; ++k) {
+                const Pt<T> pj = spts[list[k * kWave + lane]];
+                T u0 = 0, u1 = 0, z[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    z[c] = 0;
+#pragma unroll
+                for (int a = 0; a < NA; ++a) {
+                    const T d = pj.v[a] - qp.v[a];
+                    u0 += tf[0][a] * d;
+                    u1 += tf[1][a] * d;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        z[c] += nf[c][a] * d;
+                }
+                double mv[6];
+                monomials<T>(u0 * ih, u1 * ih, mv);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double e = (double)z[c];
+#pragma unroll
+                    for (int t = 0; t < 6; ++t)
+                        e = fma(-mv[t], rz[c][t], e);
+#pragma unroll
+                    for (int t = 0; t < 6; ++t)
+                        res[c][t] = fma(mv[t], e, res[c][t]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                chol6_solve(Gm, inv_d, res[c]);
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    rz[c][t] += res[c][t];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
             zx[c] = rz[c][1] * scale[1];
             zy[c] = rz[c][2] * scale[2];
             h11[c] = 2.0 * rz[c][3] * scale[3];

@@ -155,6 +155,8 @@ struct mvgd_matrix {
     void *xs = nullptr;
     size_t xs_bytes = 0;
     size_t bytes = 0;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr}; // MVGD_FLAG_TIME
+    bool have_apply = false;
 };
 
 namespace {
@@ -167,6 +169,9 @@ void release(mvgd_matrix *L)
     for (void *p : ptrs)
         if (p)
             (void)hipFreeAsync(p, L->stream);
+    for (hipEvent_t e : L->ev)
+        if (e)
+            (void)hipEventDestroy(e);
     delete L;
 }
 
@@ -303,6 +308,12 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         L->bytes += (nbytes_);                                                                    \
     } while (0)
 
+    if (p.flags & MVGD_FLAG_TIME) {
+        for (hipEvent_t &e : L->ev)
+            if (hipEventCreate(&e) != hipSuccess)
+                return fail(MVGD_EDEVICE, "hipEventCreate failed");
+        (void)hipEventRecord(L->ev[0], stream);
+    }
     // ---- 1. per-cloud bounding box and finiteness (the one synchronisation) -------------------
     int64_t *d_offs = nullptr;
     CloudStats *d_stats = nullptr;
@@ -455,12 +466,16 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.counters = L->counters;
     const size_t lds = (size_t)lds_bytes(K, (int)sizeof(Pt<T>));
     const unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
+    if (L->ev[1])
+        (void)hipEventRecord(L->ev[1], stream);
     if (n_amb == 3)
         assemble_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
     else
         assemble_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
     if (mvgd_status st = check_launch("assemble"); st != MVGD_OK)
         return st;
+    if (L->ev[2])
+        (void)hipEventRecord(L->ev[2], stream);
 #undef MVGD_ALLOC
 #undef MVGD_KEEP
     *out = L;
@@ -487,7 +502,8 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
         return fail(MVGD_EINVAL, "k must be in [5, %d] (got %d)", kMaxK, p->k);
     if (p->precision != MVGD_FP64 && p->precision != MVGD_FP32_MIXED)
         return fail(MVGD_EINVAL, "unknown precision %d", p->precision);
-    if (p->flags & ~(uint32_t)(MVGD_FLAG_LS | MVGD_FLAG_H_OVERRIDE | MVGD_FLAG_KEEP_DIAG))
+    if (p->flags & ~(uint32_t)(MVGD_FLAG_LS | MVGD_FLAG_H_OVERRIDE | MVGD_FLAG_KEEP_DIAG |
+                             MVGD_FLAG_TIME))
         return fail(MVGD_EINVAL, "unknown flag bits 0x%x", p->flags);
     if ((p->flags & MVGD_FLAG_H_OVERRIDE) && !(p->h_override > 0.0 && std::isfinite(p->h_override)))
         return fail(MVGD_EINVAL, "h_override must be positive and finite");
@@ -578,10 +594,16 @@ mvgd_status mvgd_apply(mvgd_matrix *L, const void *x, void *y, int32_t nrhs, voi
             spmv_ell_any_kernel<T><<<gb, 256, 0, s>>>(L->ell_col, val, xs, L->perm, yy, n, L->ld, slots, nrhs);
         }
     };
+    if (L->ev[3])
+        (void)hipEventRecord(L->ev[3], s);
     if (L->precision == MVGD_FP64)
         run(double());
     else
         run(float());
+    if (L->ev[4]) {
+        (void)hipEventRecord(L->ev[4], s);
+        L->have_apply = true;
+    }
     return check_launch("apply");
 }
 
@@ -648,6 +670,26 @@ mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info)
     info->n_degenerate = (int64_t)c[0];
     info->n_slow_knn = (int64_t)c[1];
     info->device_bytes = L->bytes + L->xs_bytes;
+    return MVGD_OK;
+}
+
+mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t)
+{
+    if (!L || !t)
+        return fail(MVGD_EINVAL, "NULL argument");
+    if (!L->ev[0])
+        return fail(MVGD_EINVAL, "the matrix was assembled without MVGD_FLAG_TIME");
+    if (hipStreamSynchronize(L->stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "stream synchronisation failed");
+    memset(t, 0, sizeof *t);
+    if (hipEventElapsedTime(&t->bin_ms, L->ev[0], L->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&t->assemble_ms, L->ev[1], L->ev[2]) != hipSuccess)
+        return fail(MVGD_EDEVICE, "event timing failed");
+    if (L->have_apply) {
+        if (hipEventElapsedTime(&t->apply_ms, L->ev[3], L->ev[4]) != hipSuccess)
+            return fail(MVGD_EDEVICE, "event timing failed");
+        t->have_apply = 1;
+    }
     return MVGD_OK;
 }
 

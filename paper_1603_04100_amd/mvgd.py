@@ -21,10 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libmvgd.so")
 
 MVGD_OK, MVGD_EINVAL, MVGD_ENOMEM, MVGD_EDEVICE, MVGD_EUNSUPPORTED = 0, -1, -2, -3, -4
 MVGD_FP64, MVGD_FP32_MIXED = 0, 1
-MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG = 1, 2, 4
+MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 4, 8
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
-           "mvgd_status_str", "mvgd_last_error", "mvgd_version")
+           "mvgd_timing", "mvgd_status_str", "mvgd_last_error", "mvgd_version")
 
 
 class MvgdError(RuntimeError):
@@ -46,6 +46,11 @@ class mvgd_info_t(ctypes.Structure):
                 ("n_slow_knn", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
 
 
+class mvgd_timing_t(ctypes.Structure):
+    _fields_ = [("bin_ms", ctypes.c_float), ("assemble_ms", ctypes.c_float),
+                ("apply_ms", ctypes.c_float), ("have_apply", ctypes.c_int32)]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"MVGD HIP library not built: {path} is missing "
@@ -63,6 +68,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mvgd_csr.restype = i32
     lib.mvgd_row_diag.argtypes = [vp, vp, vp, vp]
     lib.mvgd_row_diag.restype = i32
+    lib.mvgd_timing.argtypes = [vp, ctypes.POINTER(mvgd_timing_t)]
+    lib.mvgd_timing.restype = i32
     lib.mvgd_info.argtypes = [vp, ctypes.POINTER(mvgd_info_t)]
     lib.mvgd_info.restype = i32
     lib.mvgd_status_str.argtypes = [i32]
@@ -183,6 +190,13 @@ def mvgd_info(L: Matrix) -> dict:
     info = mvgd_info_t()
     _check(_lib.mvgd_info(L.handle, ctypes.byref(info)))
     return {name: getattr(info, name) for name, _ in mvgd_info_t._fields_}
+
+
+def mvgd_timing(L: Matrix) -> dict:
+    """Device durations (ms) of the last assembly / apply; needs MVGD_FLAG_TIME."""
+    t = mvgd_timing_t()
+    _check(_lib.mvgd_timing(L.handle, ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in mvgd_timing_t._fields_}
 
 
 def version() -> int:
