@@ -131,6 +131,73 @@ __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts,
     }
 }
 
+// Order the points of every cell by original index, so that sorted positions (and with them the
+// order in which the neighbour search visits candidates, hence every floating-point sum) do not
+// depend on the order of the atomic slot assignment. One thread per cell: insertion sort for small
+// cells, heap sort beyond 32 points.
+template <typename T>
+__device__ __forceinline__ void cell_swap(Pt<T> *spts, int32_t *perm, int64_t a, int64_t b)
+{
+    const Pt<T> tp = spts[a];
+    spts[a] = spts[b];
+    spts[b] = tp;
+    const int32_t ti = perm[a];
+    perm[a] = perm[b];
+    perm[b] = ti;
+}
+
+template <typename T>
+__device__ __forceinline__ void cell_sift(Pt<T> *spts, int32_t *perm, int64_t base, int64_t root,
+                                          int64_t n)
+{
+    for (;;) {
+        int64_t child = 2 * root + 1;
+        if (child >= n)
+            return;
+        if (child + 1 < n && perm[base + child + 1] > perm[base + child])
+            ++child;
+        if (perm[base + root] >= perm[base + child])
+            return;
+        cell_swap(spts, perm, base + root, base + child);
+        root = child;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cell_sort_kernel(const uint32_t *__restrict__ cell_start,
+                                                        int64_t n_cells, Pt<T> *spts, int32_t *perm)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cells)
+        return;
+    const int64_t b = cell_start[c], n = (int64_t)cell_start[c + 1] - b;
+    if (n < 2)
+        return;
+    if (n <= 32) {
+        for (int64_t i = 1; i < n; ++i) {
+            const int32_t key = perm[b + i];
+            if (perm[b + i - 1] <= key)
+                continue;
+            const Pt<T> pt = spts[b + i];
+            int64_t j = i;
+            while (j > 0 && perm[b + j - 1] > key) {
+                perm[b + j] = perm[b + j - 1];
+                spts[b + j] = spts[b + j - 1];
+                --j;
+            }
+            perm[b + j] = key;
+            spts[b + j] = pt;
+        }
+        return;
+    }
+    for (int64_t r = n / 2 - 1; r >= 0; --r)
+        cell_sift(spts, perm, b, r, n);
+    for (int64_t e = n - 1; e > 0; --e) {
+        cell_swap(spts, perm, b, b + e);
+        cell_sift(spts, perm, b, 0, e);
+    }
+}
+
 // ---------------------------------------------------------------------------------------------
 // exclusive prefix sum of uint32 (three-phase, recursive over block totals)
 // ---------------------------------------------------------------------------------------------

@@ -440,6 +440,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     }
     scatter_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_start,
                                                                d_keys, d_slots, d_spts, L->perm);
+    cell_sort_kernel<T><<<(unsigned)((cell_total + 255) / 256), 256, 0, stream>>>(
+        d_start, cell_total, d_spts, L->perm);
     if (mvgd_status st = check_launch("binning"); st != MVGD_OK)
         return st;
 
