@@ -62,7 +62,7 @@ static_assert(kBinWords * kWave * 4 <= kBndCap * kWave * 8, "histogram must fit 
 __host__ __device__ constexpr int lds_bytes(int K, int pt_bytes)
 {
     return kLdsList + K * kWave * 4 /*list*/ + 2 * kWave * 4 /*cell ranges*/ +
-           kWave * pt_bytes + 2 * kWave * 4 /*staged pos, idx*/;
+           kWave * pt_bytes + 2 * kWave * 4 /*staged pos, idx*/ + kWave * 8 /*sub-group worklist*/;
 }
 
 template <typename T, int NA>
@@ -107,7 +107,9 @@ __device__ __forceinline__ float cull_dist<double, 4>(const Pt<double> &q, const
 }
 
 // Stream every point of the cell box [bmin, bmax] of cloud g through LDS, 64 at a time, and call
-// visit(point, sorted position, original index) on every lane for every point.
+// visit(point, sorted position, original index) on every lane for every point. Staged entries
+// past the end of the stream are sentinels (position -1, coordinates 1e30: never selected), so
+// the visit loop runs in unrolled blocks of four independent LDS reads.
 template <typename T, typename F>
 __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &g, const int bmin[3],
                                            const int bmax[3], char *lds_rng, char *lds_stage,
@@ -120,7 +122,9 @@ __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &
     Pt<T> *st_pt = (Pt<T> *)lds_stage;
     int32_t *st_pos = (int32_t *)(lds_stage + kWave * sizeof(Pt<T>));
     int32_t *st_idx = st_pos + kWave;
-    const int nx = bmax[0] - bmin[0] + 1, ny = bmax[1] - bmin[1] + 1, nz = bmax[2] - bmin[2] + 1;
+    const int nx = uniform(bmax[0] - bmin[0] + 1), ny = uniform(bmax[1] - bmin[1] + 1),
+              nz = uniform(bmax[2] - bmin[2] + 1);
+    const int bx0 = uniform(bmin[0]), by0 = uniform(bmin[1]), bz0 = uniform(bmin[2]);
     const int nyz = ny * nz, ncells = nx * nyz;
     for (int cb = 0; cb < ncells; cb += kWave) {
         const int t = cb + lane;
@@ -130,13 +134,12 @@ __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &
             const int r = t - x * nyz;
             const int y = (int)((uint32_t)r / (uint32_t)nz);
             const int z = r - y * nz;
-            const uint32_t cell =
-                (uint32_t)g.cell0 + morton_of(P.parts, g, bmin[0] + x, bmin[1] + y, bmin[2] + z);
+            const uint32_t cell = (uint32_t)g.cell0 + morton_of(P.parts, g, bx0 + x, by0 + y, bz0 + z);
             st = P.cell_start[cell];
             cn = P.cell_start[cell + 1] - st;
         }
         const int incl = wave_incl_scan((int)cn);
-        const int total = __shfl(incl, kWave - 1, kWave);
+        const int total = uniform(__shfl(incl, kWave - 1, kWave));
         rng_start[lane] = (int32_t)st;
         rng_pref[lane] = incl - (int)cn;
         __syncthreads();
@@ -155,11 +158,26 @@ __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &
                 st_pt[lane] = spts[pos];
                 st_pos[lane] = pos;
                 st_idx[lane] = P.perm[pos];
+            } else {
+                Pt<T> sentinel;
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    sentinel.v[a] = (T)1e30;
+                st_pt[lane] = sentinel;
+                st_pos[lane] = -1;
+                st_idx[lane] = 0x7fffffff;
             }
             __syncthreads();
-            const int nst = min(kWave, total - sb);
-            for (int j = 0; j < nst; ++j)
-                visit(st_pt[j], st_pos[j], st_idx[j]);
+            const int nst4 = (min(kWave, total - sb) + 3) & ~3;
+            for (int j = 0; j < nst4; j += 4) {
+                const Pt<T> c0 = st_pt[j], c1 = st_pt[j + 1], c2 = st_pt[j + 2], c3 = st_pt[j + 3];
+                const int4 pp = *(const int4 *)(st_pos + j);
+                const int4 ii = *(const int4 *)(st_idx + j);
+                visit(c0, pp.x, ii.x);
+                visit(c1, pp.y, ii.y);
+                visit(c2, pp.z, ii.z);
+                visit(c3, pp.w, ii.w);
+            }
             __syncthreads();
         }
     }
@@ -334,62 +352,94 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
     const int q = (int)(s0 + (valid ? lane : 0));
     const Pt<T> qp = spts[q];
     int cc[3];
+    T uq[3]; // projected coordinates of the query
+    {
+        T x[NA];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int ax = g.axis[a];
-        const T xa = ax == 0 ? qp.v[0] : ax == 1 ? qp.v[1] : ax == 2 ? qp.v[2] : qp.v[3];
-        cc[a] = cell_coord<T>(xa, g.lo[a], g.inv_cell, g.dim[a]);
+        for (int a = 0; a < NA; ++a)
+            x[a] = qp.v[a];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            uq[a] = project<T, NA>(x, g.proj, a);
+            cc[a] = cell_coord<T>(uq[a], g.lo[a], g.inv_cell, g.dim[a]);
+        }
     }
     // every list slot holds a valid position before selection writes it
     for (int k = 0; k < K; ++k)
         list[k * kWave + lane] = q;
 
-    // ----- sub-group size: split while the search box of a sub-group is too large -------------
-    int S = kWave;
-    int mn[3], mx[3];
-    for (;;) {
+    // ----- sub-groups: split the wave's points at Morton jumps while that shrinks the boxes ------
+    // Consecutive sorted points are compact except where the Morton curve jumps; a group that
+    // straddles a jump has a box far larger than either side. A worklist of lane ranges is split
+    // at the lane pair whose Morton codes differ in the highest bit, whenever the two halves'
+    // boxes hold fewer cells than the whole.
+    const uint32_t mc = morton_of(P.parts, g, cc[0], cc[1], cc[2]);
+    const uint32_t mnext = __shfl_down(mc, 1, kWave);
+    const int hb = (lane + 1 < cnt) ? (32 - (int)__clz((int)(mc ^ mnext))) : -1;
+    int2 *work = (int2 *)(lds_stage + kWave * sizeof(Pt<T>) + 2 * kWave * 4);
+    // Search box of a lane range for radius R: the range's bounding box in projected coordinates
+    // grown by R (plus 1% of a cell, covering rounding in the binning), rounded out to cells.
+    // Every point within distance R of a query of the range lies in it.
+    auto range_box = [&](int a, int b, double R, int lo_[3], int hi_[3]) {
+        const bool in = valid && lane >= a && lane < b;
         int cells = 1;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            mn[a] = seg_min(valid ? cc[a] : 0x3fffffff, S);
-            mx[a] = seg_max(valid ? cc[a] : -1, S);
-            const int lo = max(mn[a] - g.m0, 0), hi = min(mx[a] + g.m0, g.dim[a] - 1);
-            cells *= max(hi - lo + 1, 1);
+        for (int ax = 0; ax < 3; ++ax) {
+            const double umn = seg_min(in ? (double)uq[ax] : INFINITY, kWave);
+            const double umx = seg_max(in ? (double)uq[ax] : -INFINITY, kWave);
+            const double slack = 0.01 * g.cell + 1e-6 * (fabs(umn) + fabs(umx));
+            lo_[ax] = uniform(cell_coord<double>(umn - R - slack, g.lo[ax], g.inv_cell, g.dim[ax]));
+            hi_[ax] = uniform(cell_coord<double>(umx + R + slack, g.lo[ax], g.inv_cell, g.dim[ax]));
+            cells *= hi_[ax] - lo_[ax] + 1;
         }
-        const int worst = seg_max(valid ? cells : 0, kWave);
-        if (worst <= kMaxBoxCells || S <= 8)
-            break;
-        S >>= 1;
-    }
+        return cells;
+    };
+    const double r0 = g.r0;
+    // split only ranges whose box exceeds twice a single query's box
+    const int split_min = (int)fmin(2.0 * pow(2.0 * r0 * g.inv_cell + 2.0, 3.0), 1e9);
 
     bool slow_row = false;
     const float e = kRelBand;
-    for (int sg = 0; sg < kWave / S; ++sg) {
-        const int lead = sg * S;
-        if (lead >= cnt)
-            break;
-        const bool act = valid && (lane / S == sg);
-        int bmn[3], bmx[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            bmn[a] = __shfl(mn[a], lead, kWave);
-            bmx[a] = __shfl(mx[a], lead, kWave);
-        }
-        // ----- pass 1: histogram; grow the box until every active lane counts K ------------
-        int m = g.m0;
+    int top = 1;
+    if (lane == 0)
+        work[0] = make_int2(0, cnt);
+    __syncthreads();
+    while (top > 0) {
+        --top;
+        const int ra = uniform(work[top].x), rb = uniform(work[top].y);
         int box_lo[3], box_hi[3];
+        const int cells = range_box(ra, rb, r0, box_lo, box_hi);
+        if (rb - ra >= 2 && cells > split_min) {
+            const int key = (lane >= ra && lane < rb - 1) ? hb * 64 + (63 - lane) : -1;
+            const int sk = uniform(seg_max(key, kWave));
+            const int sl = 63 - (sk & 63); // split after lane sl
+            int t0[3], t1[3];
+            const int c1 = range_box(ra, sl + 1, r0, t0, t1);
+            const int c2 = range_box(sl + 1, rb, r0, t0, t1);
+            if (c1 + c2 < cells) {
+                __syncthreads();
+                if (lane == 0) {
+                    work[top] = make_int2(sl + 1, rb);
+                    work[top + 1] = make_int2(ra, sl + 1);
+                }
+                __syncthreads();
+                top += 2;
+                continue;
+            }
+        }
+        const bool act = valid && lane >= ra && lane < rb;
+        // ----- pass 1: histogram; grow the radius until every active lane counts K -----------
+        double R = r0;
         float R2 = 0.f, s0b = 0.f;
         int total = 0;
-        for (;;) {
+        for (int grow = 0;; ++grow) {
+            if (grow > 0)
+                range_box(ra, rb, R, box_lo, box_hi);
             bool all = true;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                box_lo[a] = max(bmn[a] - m, 0);
-                box_hi[a] = min(bmx[a] + m, g.dim[a] - 1);
+            for (int a = 0; a < 3; ++a)
                 all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
-            }
-            const double rs = ((double)m - 0.01) * g.cell;
-            const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : rs * rs * (1.0 - 1e-5);
+            const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
             R2 = (float)R2d;
             if (!all)
                 R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
@@ -416,7 +466,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                     atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
                 break;
             }
-            m += max(1, m / 2);
+            R *= 1.3;
         }
 
         // ----- locate the bin of the K-th neighbour ------------------------------------------
@@ -586,6 +636,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         for (int c = 0; c < NA; ++c)
             s2[a][c] = 0.0;
     }
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
         const Pt<T> pj = spts[list[k * kWave + lane]];
         double dv[NA];
@@ -646,6 +697,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
 
     // local coordinates and the spacing h (Eq. DefH)
     T umin0 = (T)INFINITY, umax0 = -(T)INFINITY, umin1 = (T)INFINITY, umax1 = -(T)INFINITY;
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
         const Pt<T> pj = spts[list[k * kWave + lane]];
         T u0 = 0, u1 = 0;
@@ -674,6 +726,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
 #pragma unroll
         for (int t = 0; t < 6; ++t)
             rz[c][t] = 0.0;
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
         const Pt<T> pj = spts[list[k * kWave + lane]];
         T u0 = 0, u1 = 0, z[NC];
@@ -728,6 +781,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                     res[c][t] = 0.0;
                 res[c][0] = -rz[c][0]; // centre row e1 with z = 0
             }
+#pragma unroll 4
             for (int k = 0; k < K; ++k) {
                 const Pt<T> pj = spts[list[k * kWave + lane]];
                 T u0 = 0, u1 = 0, z[NC];
@@ -803,6 +857,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
             for (int t = 0; t < 6; ++t)
                 res[t] = dl[t];
             res[0] -= y[0]; // centre row e1: (V y)_0 = y0
+#pragma unroll 4
             for (int k = 0; k < K; ++k) {
                 const Pt<T> pj = spts[list[k * kWave + lane]];
                 T u0 = 0, u1 = 0;
@@ -833,6 +888,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
     const int64_t ld = P.ld;
     P.ell_col[q] = q;
     val[q] = degenerate ? (T)0 : (T)(y[0] - tau);
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
         const int pos = list[k * kWave + lane];
         double w = 0.0;

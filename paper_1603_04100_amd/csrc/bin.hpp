@@ -11,10 +11,12 @@
 namespace mvgd {
 
 struct CloudStats {  // ordered-encoded doubles; see ord_encode
-    unsigned long long mn[4];
+    unsigned long long mn[4];   // ambient coordinates
     unsigned long long mx[4];
+    unsigned long long pmn[3];  // projected coordinates
+    unsigned long long pmx[3];
     unsigned long long nonfinite;
-    unsigned long long pad[7];
+    unsigned long long pad;
 };
 
 __global__ void stats_init_kernel(CloudStats *st, int n_clouds)
@@ -26,41 +28,63 @@ __global__ void stats_init_kernel(CloudStats *st, int n_clouds)
         st[c].mn[a] = ~0ull;
         st[c].mx[a] = 0ull;
     }
+    for (int a = 0; a < 3; ++a) {
+        st[c].pmn[a] = ~0ull;
+        st[c].pmx[a] = 0ull;
+    }
     st[c].nonfinite = 0;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts, int n_amb,
-                                                   const int64_t *__restrict__ offsets,
+template <typename T, int NA>
+__global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts,
+                                                   const int64_t *__restrict__ offsets, Proj pr,
                                                    CloudStats *st)
 {
     const int c = blockIdx.y;
     const int64_t b = offsets[c], e = offsets[c + 1];
-    double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-    double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    double mn[7], mx[7]; // NA ambient, then 3 projected
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+        mn[a] = INFINITY;
+        mx[a] = -INFINITY;
+    }
     unsigned long long bad = 0;
     for (int64_t i = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < e;
          i += (int64_t)gridDim.x * blockDim.x) {
-        for (int a = 0; a < n_amb; ++a) {
-            double v = (double)pts[i * n_amb + a];
-            if (!isfinite(v)) {
-                ++bad;
-                continue;
-            }
-            mn[a] = fmin(mn[a], v);
-            mx[a] = fmax(mx[a], v);
+        T x[NA];
+        bool fin = true;
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            x[a] = pts[i * NA + a];
+            fin = fin && isfinite((double)x[a]);
+        }
+        if (!fin) {
+            ++bad;
+            continue;
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            mn[a] = fmin(mn[a], (double)x[a]);
+            mx[a] = fmax(mx[a], (double)x[a]);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double u = (double)project<T, NA>(x, pr, a);
+            mn[4 + a] = fmin(mn[4 + a], u);
+            mx[4 + a] = fmax(mx[4 + a], u);
         }
     }
-    __shared__ double smn[4][4], smx[4][4];
+    __shared__ double smn[4][7], smx[4][7];
     __shared__ unsigned long long sbad[4];
     const int w = threadIdx.x / kWave, l = lane_id();
-    for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
         mn[a] = seg_min(mn[a], kWave);
         mx[a] = seg_max(mx[a], kWave);
     }
     bad = wave_sum(bad);
     if (l == 0) {
-        for (int a = 0; a < 4; ++a) {
+        for (int a = 0; a < 7; ++a) {
             smn[w][a] = mn[a];
             smx[w][a] = mx[a];
         }
@@ -69,15 +93,19 @@ __global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts, in
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = blockDim.x / kWave;
-        for (int a = 0; a < n_amb; ++a) {
+        for (int a = 0; a < 7; ++a) {
+            if (a >= NA && a < 4)
+                continue;
             double lo = smn[0][a], hi = smx[0][a];
             for (int k = 1; k < nw; ++k) {
                 lo = fmin(lo, smn[k][a]);
                 hi = fmax(hi, smx[k][a]);
             }
             if (lo <= hi) {
-                atomicMin(&st[c].mn[a], ord_encode(lo));
-                atomicMax(&st[c].mx[a], ord_encode(hi));
+                unsigned long long *pmn = a < 4 ? &st[c].mn[a] : &st[c].pmn[a - 4];
+                unsigned long long *pmx = a < 4 ? &st[c].mx[a] : &st[c].pmx[a - 4];
+                atomicMin(pmn, ord_encode(lo));
+                atomicMax(pmx, ord_encode(hi));
             }
         }
         unsigned long long tb = 0;
@@ -88,8 +116,8 @@ __global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts, in
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void key_kernel(const T *__restrict__ pts, int n_amb,
+template <typename T, int NA>
+__global__ __launch_bounds__(256) void key_kernel(const T *__restrict__ pts,
                                                   const CloudGrid *__restrict__ grids,
                                                   const uint32_t *__restrict__ parts,
                                                   uint32_t *__restrict__ counts,
@@ -100,9 +128,14 @@ __global__ __launch_bounds__(256) void key_kernel(const T *__restrict__ pts, int
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = g.row0 + t;
+        T x[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+            x[a] = pts[i * NA + a];
         int cc[3];
+#pragma unroll
         for (int a = 0; a < 3; ++a)
-            cc[a] = cell_coord<T>(pts[i * n_amb + g.axis[a]], g.lo[a], g.inv_cell, g.dim[a]);
+            cc[a] = cell_coord<T>(project<T, NA>(x, g.proj, a), g.lo[a], g.inv_cell, g.dim[a]);
         const uint32_t key = (uint32_t)g.cell0 + morton_of(parts, g, cc[0], cc[1], cc[2]);
         keys[i] = key;
         slots[i] = atomicAdd(&counts[key], 1u);

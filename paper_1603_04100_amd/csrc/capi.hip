@@ -180,24 +180,40 @@ struct HostGrid {
     std::vector<uint32_t> parts;
 };
 
-// Cell grid of one cloud from its bounding box: binning axes = the three largest extents; the
-// cell edge follows the estimated K-th neighbour distance of a surface sample.
-void plan_grid(const double *mn, const double *mx, int n_amb, int64_t n, int K, int64_t row0,
-               HostGrid &hg)
+// The fixed binning projection (rows orthonormal): identity for n = 3, a generic 3x4 matrix for
+// n = 4 (see Proj in common.hpp).
+Proj binning_projection(int n_amb)
+{
+    Proj pr;
+    memset(&pr, 0, sizeof pr);
+    if (n_amb == 3) {
+        for (int a = 0; a < 3; ++a)
+            pr.W[a][a] = 1.0;
+        return pr;
+    }
+    static const double W4[3][4] = {
+        {-0.5049971086679399, -0.7970289394280843, -0.09843310179405794, 0.3162810687068779},
+        {-0.47371621671260017, 0.21177439071878815, -0.7273779116057677, -0.4490722961475343},
+        {-0.4950075093018881, 0.01078809292873078, 0.6682902330051771, -0.5551930720529468}};
+    memcpy(pr.W, W4, sizeof W4);
+    return pr;
+}
+
+// Cell grid of one cloud from its bounding boxes (ambient: diameter; projected: the grid). The
+// cell edge follows the estimated K-th neighbour distance of a surface sample: the area of a
+// closed surface is taken as about half the surface of its projected bounding box.
+void plan_grid(const double *mn, const double *mx, const double *pmn, const double *pmx,
+               const Proj &pr, int n_amb, int64_t n, int K, int64_t row0, HostGrid &hg)
 {
     const double alpha = env_double("MVGD_CELL_ALPHA", 0.6);
-    const double mu = env_double("MVGD_MARGIN_MU", 1.5);
-    double E[4];
-    int ax[4] = {0, 1, 2, 3};
+    const double mu = env_double("MVGD_MARGIN_MU", 1.7);
+    double diam2 = 0.0;
     for (int a = 0; a < n_amb; ++a)
-        E[a] = mx[a] - mn[a];
-    std::stable_sort(ax, ax + n_amb, [&](int x, int y) { return E[x] > E[y]; });
-    double Eb[3], diam2 = 0.0;
-    for (int a = 0; a < n_amb; ++a)
-        diam2 += E[a] * E[a];
+        diam2 += (mx[a] - mn[a]) * (mx[a] - mn[a]);
+    double Eb[3];
     for (int a = 0; a < 3; ++a)
-        Eb[a] = E[ax[a]];
-    const double emax = std::max(Eb[0], 1e-300);
+        Eb[a] = pmx[a] - pmn[a];
+    const double emax = std::max(std::max(Eb[0], std::max(Eb[1], Eb[2])), 1e-300);
     double Ef[3];
     for (int a = 0; a < 3; ++a)
         Ef[a] = std::max(Eb[a], emax * 1e-3);
@@ -227,15 +243,15 @@ void plan_grid(const double *mn, const double *mx, int n_amb, int64_t n, int K, 
     memset(&g, 0, sizeof g);
     g.row0 = row0;
     g.n = n;
+    g.proj = pr;
     for (int a = 0; a < 3; ++a) {
-        g.lo[a] = mn[ax[a]];
+        g.lo[a] = pmn[a];
         g.dim[a] = (int32_t)dim[a];
-        g.axis[a] = ax[a];
     }
     g.cell = cell;
     g.inv_cell = 1.0 / cell;
     g.diam2 = diam2;
-    g.m0 = (int32_t)std::min(64.0, std::max(1.0, std::ceil(mu * dk / cell)));
+    g.r0 = mu * dk;
     // Morton part tables: bit l of the coordinate along axis a goes to its interleaved position.
     int bits[3], maxb = 0;
     for (int a = 0; a < 3; ++a) {
@@ -315,6 +331,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         (void)hipEventRecord(L->ev[0], stream);
     }
     // ---- 1. per-cloud bounding box and finiteness (the one synchronisation) -------------------
+    const Proj proj = binning_projection(n_amb);
     int64_t *d_offs = nullptr;
     CloudStats *d_stats = nullptr;
     MVGD_ALLOC(d_offs, sizeof(int64_t) * offs.size(), "offsets");
@@ -328,7 +345,10 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         for (int c = 0; c < n_clouds; ++c)
             max_n = std::max(max_n, offs[c + 1] - offs[c]);
         const int bx = (int)std::min<int64_t>(1024, (max_n + 255) / 256);
-        bbox_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, d_offs, d_stats);
+        if (n_amb == 3)
+            bbox_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_offs, proj, d_stats);
+        else
+            bbox_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_offs, proj, d_stats);
     }
     if (mvgd_status st = check_launch("bbox"); st != MVGD_OK)
         return st;
@@ -352,13 +372,17 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         if (hs[c].nonfinite)
             return fail(MVGD_EINVAL, "cloud %d has %llu non-finite coordinates", c,
                         (unsigned long long)hs[c].nonfinite);
-        double mn[4], mx[4];
+        double mn[4], mx[4], pmn[3], pmx[3];
         for (int a = 0; a < n_amb; ++a) {
             mn[a] = decode(hs[c].mn[a]);
             mx[a] = decode(hs[c].mx[a]);
         }
+        for (int a = 0; a < 3; ++a) {
+            pmn[a] = decode(hs[c].pmn[a]);
+            pmx[a] = decode(hs[c].pmx[a]);
+        }
         const int64_t n = offs[c + 1] - offs[c];
-        plan_grid(mn, mx, n_amb, n, K, offs[c], hg[c]);
+        plan_grid(mn, mx, pmn, pmx, proj, n_amb, n, K, offs[c], hg[c]);
         CloudGrid &g = hg[c].g;
         g.cell0 = cell_total;
         g.group0 = group_total;
@@ -417,8 +441,12 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     for (int c = 0; c < n_clouds; ++c)
         max_n = std::max(max_n, offs[c + 1] - offs[c]);
     const int bx = (int)std::min<int64_t>(2048, (max_n + 255) / 256);
-    key_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_parts,
-                                                           d_counts, d_keys, d_slots);
+    if (n_amb == 3)
+        key_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
+                                                                  d_counts, d_keys, d_slots);
+    else
+        key_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
+                                                                  d_counts, d_keys, d_slots);
     // exclusive scan of the counts, level by level
     {
         const uint32_t *in = d_counts;

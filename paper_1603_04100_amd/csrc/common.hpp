@@ -14,24 +14,45 @@ constexpr int kBndCap = 16;            // boundary candidates resolved exactly p
 constexpr int kMaxBoxCells = 4096;     // sub-groups are split while their box is larger
 constexpr float kRelBand = 4e-6f;      // bound on |f32 distance^2 - exact key| / key (+ margin)
 
-// One cloud's cell grid. Points are binned on three of the ambient coordinates (the three of
-// largest extent); cells are numbered in Morton order so that a run of consecutive sorted
-// points is spatially compact.
+// Orthonormal projection R^n -> R^3 on which the points are binned (rows of W). For n = 3 it is
+// the identity. For n = 4 it is a fixed generic orthonormal 3x4 matrix: binning on three of the
+// four coordinates would fold symmetric sheets onto each other (e.g. phi and -phi of a flat
+// torus (cos t, sin t, cos p, sin p)), doubling the candidates of every search. Any orthonormal
+// projection is 1-Lipschitz, so a cell box of radius R around a query still contains every
+// point within distance R of it.
+struct Proj {
+    double W[3][4];
+};
+
+// One cloud's cell grid over the projected coordinates; cells are numbered in Morton order so
+// that a run of consecutive sorted points is spatially compact.
 struct CloudGrid {
     int64_t row0;      // first global row (= first sorted position) of the cloud
     int64_t n;         // points in the cloud
     int64_t cell0;     // first entry of the cloud in the global cell table
     int64_t group0;    // first 64-point work group of the cloud
     int64_t part0;     // offset of the cloud's Morton part tables (dim[0]+dim[1]+dim[2] entries)
-    double lo[3];      // grid origin along the binning axes
+    Proj proj;         // binning projection
+    double lo[3];      // grid origin along the projected axes
     double inv_cell;   // 1 / cell edge
     double cell;       // cell edge
     double diam2;      // squared diameter of the cloud's bounding box (all ambient axes)
-    int32_t dim[3];    // cells per binning axis (powers of two)
-    int32_t axis[3];   // ambient coordinate of each binning axis
-    int32_t m0;        // initial search margin, in cells
+    double r0;         // initial search radius (real units)
+    int32_t dim[3];    // cells per projected axis (powers of two)
     int32_t pad;
 };
+
+// projected coordinate a of a point (explicit FMA chain: binning and query lookup evaluate it
+// identically)
+template <typename T, int NA>
+__device__ __forceinline__ T project(const T *x, const Proj &pr, int a)
+{
+    T u = x[0] * (T)pr.W[a][0];
+#pragma unroll
+    for (int k = 1; k < NA; ++k)
+        u = fma(x[k], (T)pr.W[a][k], u);
+    return u;
+}
 
 // Point storage: coordinates padded to four components.
 template <typename T> struct Pt;
@@ -54,6 +75,8 @@ template <typename T>
 __device__ __forceinline__ int cell_coord(T x, double lo, double inv, int dim)
 {
     T t = (x - (T)lo) * (T)inv;
+    t = t > (T)-1 ? t : (T)-1; // also maps NaN to -1
+    t = t < (T)dim ? t : (T)dim;
     int c = (int)floor(t);
     c = c < 0 ? 0 : c;
     return c > dim - 1 ? dim - 1 : c;
