@@ -79,6 +79,9 @@ typedef struct {
     int64_t n_slow_knn;    /* rows whose neighbour search took the exhaustive fallback
                               (exact ties or extreme clustering); informational */
     size_t device_bytes;   /* device memory held by the handle */
+    int64_t n_subgroups;   /* neighbour-search sub-groups (ranges of 64-point groups) */
+    int64_t n_streamed;    /* candidate points streamed through the search, all passes */
+    int64_t n_growths;     /* search-radius growths (a sub-group's radius was too small) */
 } mvgd_info_t;
 
 /*

@@ -35,6 +35,7 @@ namespace mvgd {
 struct AsmParams {
     const void *spts;           // Pt<T>[n_total], cell-sorted
     const int32_t *perm;        // sorted position -> global row
+    const int32_t *iperm;       // global row -> sorted position
     const uint32_t *cell_start; // global cell table, exclusive prefix (cells + 1)
     const uint32_t *parts;      // Morton part tables
     const CloudGrid *grids;
@@ -50,12 +51,13 @@ struct AsmParams {
     void *ell_val;              // [K+1][ld] weights (T)
     double *row_h;              // optional, sorted order
     uint8_t *row_flags;         // optional, sorted order
-    unsigned long long *counters; // [0] degenerate rows, [1] slow-path rows, [2] internal errors
+    unsigned long long *counters; // [0] degenerate rows, [1] slow-path rows, [2] internal errors,
+                                  // [3] sub-groups, [4] candidates streamed, [5] radius growths
 };
 
 // LDS layout of one wave (bytes)
 constexpr int kLdsHist = 0;                                 // u32 [kBinWords][64] | f64 [kBndCap][64]
-constexpr int kLdsBndPos = kLdsHist + kBndCap * kWave * 8;  // i32 [kBndCap][64]
+constexpr int kLdsBndPos = kLdsHist + kBndCap * kWave * 8;  // i32 [kBndCap][64] (indices)
 constexpr int kLdsList = kLdsBndPos + kBndCap * kWave * 4;  // i32 [K][64]
 static_assert(kBinWords * kWave * 4 <= kBndCap * kWave * 8, "histogram must fit the key area");
 
@@ -111,7 +113,7 @@ __device__ __forceinline__ float cull_dist<double, 4>(const Pt<double> &q, const
 // past the end of the stream are sentinels (position -1, coordinates 1e30: never selected), so
 // the visit loop runs in unrolled blocks of four independent LDS reads.
 template <typename T, typename F>
-__device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &g, const int bmin[3],
+__device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g, const int bmin[3],
                                            const int bmax[3], char *lds_rng, char *lds_stage,
                                            F &&visit)
 {
@@ -126,6 +128,7 @@ __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &
               nz = uniform(bmax[2] - bmin[2] + 1);
     const int bx0 = uniform(bmin[0]), by0 = uniform(bmin[1]), bz0 = uniform(bmin[2]);
     const int nyz = ny * nz, ncells = nx * nyz;
+    int streamed = 0;
     for (int cb = 0; cb < ncells; cb += kWave) {
         const int t = cb + lane;
         uint32_t st = 0, cn = 0;
@@ -140,6 +143,7 @@ __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &
         }
         const int incl = wave_incl_scan((int)cn);
         const int total = uniform(__shfl(incl, kWave - 1, kWave));
+        streamed += total;
         rng_start[lane] = (int32_t)st;
         rng_pref[lane] = incl - (int)cn;
         __syncthreads();
@@ -181,6 +185,7 @@ __device__ __forceinline__ void stream_box(const AsmParams &P, const CloudGrid &
             __syncthreads();
         }
     }
+    return streamed;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -364,9 +369,12 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
             cc[a] = cell_coord<T>(uq[a], g.lo[a], g.inv_cell, g.dim[a]);
         }
     }
-    // every list slot holds a valid position before selection writes it
+    // During selection the list holds original indices (the order of a cell's points in the
+    // sorted array depends on atomic slot order, so positions are not canonical); every slot
+    // holds a valid index before selection writes it.
+    const int qidx = P.perm[q];
     for (int k = 0; k < K; ++k)
-        list[k * kWave + lane] = q;
+        list[k * kWave + lane] = qidx;
 
     // ----- sub-groups: split the wave's points at Morton jumps while that shrinks the boxes ------
     // Consecutive sorted points are compact except where the Morton curve jumps; a group that
@@ -400,6 +408,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
 
     bool slow_row = false;
     const float e = kRelBand;
+    int n_streamed = 0, n_sub = 0, n_grow = 0;
     int top = 1;
     if (lane == 0)
         work[0] = make_int2(0, cnt);
@@ -428,13 +437,16 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
             }
         }
         const bool act = valid && lane >= ra && lane < rb;
+        ++n_sub;
         // ----- pass 1: histogram; grow the radius until every active lane counts K -----------
         double R = r0;
         float R2 = 0.f, s0b = 0.f;
         int total = 0;
         for (int grow = 0;; ++grow) {
-            if (grow > 0)
+            if (grow > 0) {
                 range_box(ra, rb, R, box_lo, box_hi);
+                ++n_grow;
+            }
             bool all = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -449,7 +461,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                 hist[w * kWave + lane] = 0u;
             total = 0;
             __syncthreads();
-            stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+            n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
                           [&](const Pt<T> &c, int pos, int idx) {
                               if (!act || pos == q)
                                   return;
@@ -498,7 +510,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
             for (int w = 0; w < kBinWords; ++w)
                 hist[w * kWave + lane] = 0u;
             __syncthreads();
-            stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+            n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
                           [&](const Pt<T> &c, int pos, int idx) {
                               if (!refine || pos == q)
                                   return;
@@ -538,19 +550,19 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         // ----- pass 2: classify --------------------------------------------------------------
         const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
         int nin = 0, nb = 0;
-        stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+        n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
                       [&](const Pt<T> &c, int pos, int idx) {
                           if (!act || pos == q)
                               return;
                           const float f = cull_dist<T, NA>(qp, c);
                           if (f * (1.f + e) < lo_t) {
                               if (nin < K)
-                                  list[nin * kWave + lane] = pos;
+                                  list[nin * kWave + lane] = idx;
                               ++nin;
                           } else if (f * (1.f - e) <= hi_t) {
                               if (nb < kBndCap) {
                                   bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
-                                  bndpos[nb * kWave + lane] = pos;
+                                  bndpos[nb * kWave + lane] = idx;
                               }
                               ++nb;
                           }
@@ -563,13 +575,11 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         if (act && !slow) {
             for (int bi = 0; bi < nb; ++bi) {
                 const double kb = bndkey[bi * kWave + lane];
-                const int pb = bndpos[bi * kWave + lane];
+                const int pb = bndpos[bi * kWave + lane]; // original index
                 int rank = 0;
                 for (int bj = 0; bj < nb; ++bj) {
                     const double kj = bndkey[bj * kWave + lane];
-                    if (kj < kb)
-                        ++rank;
-                    else if (kj == kb && bj != bi && P.perm[bndpos[bj * kWave + lane]] < P.perm[pb])
+                    if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
                         ++rank;
                 }
                 if (rank < r)
@@ -588,7 +598,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                 double best_k = INFINITY;
                 int best_i = 0x7fffffff, best_p = -1;
                 const bool want = slow && sidx < rr;
-                stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
+                n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
                               [&](const Pt<T> &c, int pos, int idx) {
                                   if (!want || pos == q)
                                       return;
@@ -603,9 +613,7 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                                   }
                               });
                 if (want) {
-                    if (best_p < 0)
-                        best_p = q;
-                    list[(nin_s + sidx) * kWave + lane] = best_p;
+                    list[(nin_s + sidx) * kWave + lane] = best_p < 0 ? qidx : best_i;
                     last_k = best_k;
                     last_i = best_i;
                     if (best_i == 0x7fffffff)
@@ -618,9 +626,28 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         __syncthreads();
     }
 
+    if (lane == 0) {
+        atomicAdd(&P.counters[3], (unsigned long long)n_sub);
+        atomicAdd(&P.counters[4], (unsigned long long)n_streamed);
+        atomicAdd(&P.counters[5], (unsigned long long)n_grow);
+    }
     // =============================== per-lane fit =============================================
     if (!valid)
         return;
+    // canonical neighbour order: ascending original index (the order of the rows of V in the
+    // paper's normal equations), then back to sorted positions for local gathers
+    for (int a = 1; a < K; ++a) {
+        const int v = list[a * kWave + lane];
+        int b = a - 1;
+        while (b >= 0 && list[b * kWave + lane] > v) {
+            list[(b + 1) * kWave + lane] = list[b * kWave + lane];
+            --b;
+        }
+        list[(b + 1) * kWave + lane] = v;
+    }
+#pragma unroll 4
+    for (int k = 0; k < K; ++k)
+        list[k * kWave + lane] = P.iperm[list[k * kWave + lane]];
     T *val = (T *)P.ell_val;
     double qd[NA];
 #pragma unroll

@@ -3,7 +3,8 @@
 // bbox_kernel      per-cloud bounding box over all ambient coordinates + non-finite count
 // key_kernel       cell key of every point and its slot inside the cell (atomic count)
 // scan_*           exclusive prefix sum of the cell counts -> cell start offsets
-// scatter_kernel   cell-sorted copy of the points (padded to 4 components) + permutation
+// scatter_kernel   cell-sorted copy of the points (padded to 4 components), permutation and
+//                  its inverse (order inside a cell follows the atomic slots)
 #pragma once
 
 #include "common.hpp"
@@ -149,7 +150,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts,
                                                       const uint32_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ slots,
                                                       Pt<T> *__restrict__ spts,
-                                                      int32_t *__restrict__ perm)
+                                                      int32_t *__restrict__ perm,
+                                                      int32_t *__restrict__ iperm)
 {
     const CloudGrid g = grids[blockIdx.y];
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
@@ -161,73 +163,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts,
             p.v[a] = a < n_amb ? pts[i * n_amb + a] : (T)0;
         spts[pos] = p;
         perm[pos] = (int32_t)i;
-    }
-}
-
-// Order the points of every cell by original index, so that sorted positions (and with them the
-// order in which the neighbour search visits candidates, hence every floating-point sum) do not
-// depend on the order of the atomic slot assignment. One thread per cell: insertion sort for small
-// cells, heap sort beyond 32 points.
-template <typename T>
-__device__ __forceinline__ void cell_swap(Pt<T> *spts, int32_t *perm, int64_t a, int64_t b)
-{
-    const Pt<T> tp = spts[a];
-    spts[a] = spts[b];
-    spts[b] = tp;
-    const int32_t ti = perm[a];
-    perm[a] = perm[b];
-    perm[b] = ti;
-}
-
-template <typename T>
-__device__ __forceinline__ void cell_sift(Pt<T> *spts, int32_t *perm, int64_t base, int64_t root,
-                                          int64_t n)
-{
-    for (;;) {
-        int64_t child = 2 * root + 1;
-        if (child >= n)
-            return;
-        if (child + 1 < n && perm[base + child + 1] > perm[base + child])
-            ++child;
-        if (perm[base + root] >= perm[base + child])
-            return;
-        cell_swap(spts, perm, base + root, base + child);
-        root = child;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void cell_sort_kernel(const uint32_t *__restrict__ cell_start,
-                                                        int64_t n_cells, Pt<T> *spts, int32_t *perm)
-{
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cells)
-        return;
-    const int64_t b = cell_start[c], n = (int64_t)cell_start[c + 1] - b;
-    if (n < 2)
-        return;
-    if (n <= 32) {
-        for (int64_t i = 1; i < n; ++i) {
-            const int32_t key = perm[b + i];
-            if (perm[b + i - 1] <= key)
-                continue;
-            const Pt<T> pt = spts[b + i];
-            int64_t j = i;
-            while (j > 0 && perm[b + j - 1] > key) {
-                perm[b + j] = perm[b + j - 1];
-                spts[b + j] = spts[b + j - 1];
-                --j;
-            }
-            perm[b + j] = key;
-            spts[b + j] = pt;
-        }
-        return;
-    }
-    for (int64_t r = n / 2 - 1; r >= 0; --r)
-        cell_sift(spts, perm, b, r, n);
-    for (int64_t e = n - 1; e > 0; --e) {
-        cell_swap(spts, perm, b, b + e);
-        cell_sift(spts, perm, b, 0, e);
+        iperm[i] = (int32_t)pos;
     }
 }
 

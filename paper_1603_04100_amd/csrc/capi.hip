@@ -344,7 +344,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         int64_t max_n = 0;
         for (int c = 0; c < n_clouds; ++c)
             max_n = std::max(max_n, offs[c + 1] - offs[c]);
-        const int bx = (int)std::min<int64_t>(1024, (max_n + 255) / 256);
+        const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(512, (max_n + 2047) / 2048));
         if (n_amb == 3)
             bbox_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_offs, proj, d_stats);
         else
@@ -406,6 +406,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     MVGD_ALLOC(d_keys, sizeof(uint32_t) * n_total, "keys");
     MVGD_ALLOC(d_slots, sizeof(uint32_t) * n_total, "slots");
     MVGD_ALLOC(d_spts, sizeof(Pt<T>) * n_total, "sorted points");
+    int32_t *d_iperm;
+    MVGD_ALLOC(d_iperm, sizeof(int32_t) * n_total, "inverse permutation");
     // scan levels
     std::vector<int64_t> lvl_n;
     for (int64_t m = cell_total; m > 1; m = (m + kScanTile - 1) / kScanTile)
@@ -423,7 +425,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     MVGD_KEEP(L->ell_col, sizeof(int32_t) * (size_t)(K + 1) * L->ld, "columns");
     MVGD_KEEP(L->ell_val, vsz * (size_t)(K + 1) * L->ld, "values");
     MVGD_KEEP(L->grids, sizeof(CloudGrid) * n_clouds, "grids");
-    MVGD_KEEP(L->counters, sizeof(unsigned long long) * 4, "counters");
+    MVGD_KEEP(L->counters, sizeof(unsigned long long) * 8, "counters");
     if (p.flags & MVGD_FLAG_KEEP_DIAG) {
         MVGD_KEEP(L->row_h, sizeof(double) * n_total, "row h");
         MVGD_KEEP(L->row_flags, n_total, "row flags");
@@ -435,7 +437,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         hipMemcpyAsync(L->grids, grids.data(), sizeof(CloudGrid) * n_clouds,
                        hipMemcpyHostToDevice, stream) != hipSuccess ||
         hipMemsetAsync(d_counts, 0, sizeof(uint32_t) * cell_total, stream) != hipSuccess ||
-        hipMemsetAsync(L->counters, 0, sizeof(unsigned long long) * 4, stream) != hipSuccess)
+        hipMemsetAsync(L->counters, 0, sizeof(unsigned long long) * 8, stream) != hipSuccess)
         return fail(MVGD_EDEVICE, "grid upload failed");
     int64_t max_n = 0;
     for (int c = 0; c < n_clouds; ++c)
@@ -467,9 +469,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         scan_total_kernel<<<1, 64, 0, stream>>>(d_counts, d_start, cell_total);
     }
     scatter_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_start,
-                                                               d_keys, d_slots, d_spts, L->perm);
-    cell_sort_kernel<T><<<(unsigned)((cell_total + 255) / 256), 256, 0, stream>>>(
-        d_start, cell_total, d_spts, L->perm);
+                                                               d_keys, d_slots, d_spts, L->perm,
+                                                               d_iperm);
     if (mvgd_status st = check_launch("binning"); st != MVGD_OK)
         return st;
 
@@ -478,6 +479,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     memset(&ap, 0, sizeof ap);
     ap.spts = d_spts;
     ap.perm = L->perm;
+    ap.iperm = d_iperm;
     ap.cell_start = d_start;
     ap.parts = d_parts;
     ap.grids = L->grids;
@@ -684,7 +686,7 @@ mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info)
 {
     if (!L || !info)
         return fail(MVGD_EINVAL, "NULL argument");
-    unsigned long long c[4] = {0, 0, 0, 0};
+    unsigned long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (hipMemcpyAsync(c, L->counters, sizeof c, hipMemcpyDeviceToHost, L->stream) != hipSuccess ||
         hipStreamSynchronize(L->stream) != hipSuccess)
         return fail(MVGD_EDEVICE, "reading counters failed");
@@ -700,6 +702,9 @@ mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info)
     info->n_degenerate = (int64_t)c[0];
     info->n_slow_knn = (int64_t)c[1];
     info->device_bytes = L->bytes + L->xs_bytes;
+    info->n_subgroups = (int64_t)c[3];
+    info->n_streamed = (int64_t)c[4];
+    info->n_growths = (int64_t)c[5];
     return MVGD_OK;
 }
 

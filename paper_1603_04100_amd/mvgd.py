@@ -43,7 +43,9 @@ class mvgd_info_t(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_clouds", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("nnz", ctypes.c_int64), ("precision", ctypes.c_int32),
                 ("n_ambient", ctypes.c_int32), ("n_degenerate", ctypes.c_int64),
-                ("n_slow_knn", ctypes.c_int64), ("device_bytes", ctypes.c_size_t)]
+                ("n_slow_knn", ctypes.c_int64), ("device_bytes", ctypes.c_size_t),
+                ("n_subgroups", ctypes.c_int64), ("n_streamed", ctypes.c_int64),
+                ("n_growths", ctypes.c_int64)]
 
 
 class mvgd_timing_t(ctypes.Structure):
