@@ -109,13 +109,14 @@ __device__ __forceinline__ float cull_dist<double, 4>(const Pt<double> &q, const
 }
 
 // Stream every point of the cell box [bmin, bmax] of cloud g through LDS, 64 at a time, and call
-// visit(point, sorted position, original index) on every lane for every point. Staged entries
-// past the end of the stream are sentinels (position -1, coordinates 1e30: never selected), so
-// the visit loop runs in unrolled blocks of four independent LDS reads.
-template <typename T, typename F>
+// visit(f, point, sorted position, original index) on every lane for every point, where f is the
+// culling distance of the point to the lane's query (+inf for inactive lanes and for the query
+// itself). Staged entries past the end of the stream are sentinels (position -1, coordinates
+// 1e30), so the visit loop runs in blocks of four whose LDS reads are issued one block ahead.
+template <typename T, int NA, typename F>
 __device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g, const int bmin[3],
-                                           const int bmax[3], char *lds_rng, char *lds_stage,
-                                           F &&visit)
+                                          const int bmax[3], char *lds_rng, char *lds_stage,
+                                          const Pt<T> &qp, int q, bool act, F &&visit)
 {
     const int lane = lane_id();
     const Pt<T> *spts = (const Pt<T> *)P.spts;
@@ -173,14 +174,23 @@ __device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g
             }
             __syncthreads();
             const int nst4 = (min(kWave, total - sb) + 3) & ~3;
+            Pt<T> c0 = st_pt[0], c1 = st_pt[1], c2 = st_pt[2], c3 = st_pt[3];
+            int4 pp = *(const int4 *)(st_pos), ii = *(const int4 *)(st_idx);
             for (int j = 0; j < nst4; j += 4) {
-                const Pt<T> c0 = st_pt[j], c1 = st_pt[j + 1], c2 = st_pt[j + 2], c3 = st_pt[j + 3];
-                const int4 pp = *(const int4 *)(st_pos + j);
-                const int4 ii = *(const int4 *)(st_idx + j);
-                visit(c0, pp.x, ii.x);
-                visit(c1, pp.y, ii.y);
-                visit(c2, pp.z, ii.z);
-                visit(c3, pp.w, ii.w);
+                const int jn = min(j + 4, kWave - 4);
+                const Pt<T> n0 = st_pt[jn], n1 = st_pt[jn + 1], n2 = st_pt[jn + 2], n3 = st_pt[jn + 3];
+                const int4 np = *(const int4 *)(st_pos + jn), ni = *(const int4 *)(st_idx + jn);
+                const float inf = INFINITY;
+                const float f0 = (act && pp.x != q) ? cull_dist<T, NA>(qp, c0) : inf;
+                const float f1 = (act && pp.y != q) ? cull_dist<T, NA>(qp, c1) : inf;
+                const float f2 = (act && pp.z != q) ? cull_dist<T, NA>(qp, c2) : inf;
+                const float f3 = (act && pp.w != q) ? cull_dist<T, NA>(qp, c3) : inf;
+                visit(f0, c0, pp.x, ii.x);
+                visit(f1, c1, pp.y, ii.y);
+                visit(f2, c2, pp.z, ii.z);
+                visit(f3, c3, pp.w, ii.w);
+                c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+                pp = np; ii = ni;
             }
             __syncthreads();
         }
@@ -461,11 +471,8 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                 hist[w * kWave + lane] = 0u;
             total = 0;
             __syncthreads();
-            n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
-                          [&](const Pt<T> &c, int pos, int idx) {
-                              if (!act || pos == q)
-                                  return;
-                              const float f = cull_dist<T, NA>(qp, c);
+            n_streamed += stream_box<T, NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, qp, q, act,
+                          [&](float f, const Pt<T> &c, int pos, int idx) {
                               if (f <= R2) {
                                   ++total;
                                   const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
@@ -502,6 +509,20 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         }
         const float wb = R2 / (float)kBins;
         float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
+        // Later passes only need candidates with f <= hi (times the band): stream the box of the
+        // largest such radius over the range's lanes instead of the pass-1 box.
+        int nbox_lo[3], nbox_hi[3];
+        {
+            const float hmax = seg_max(act ? (overflow ? R2 : hi_f) : 0.f, kWave);
+            const double rn = sqrt((double)hmax * (1.0 + 4.0 * (double)e)) * (1.0 + 1e-5);
+            if (rn < R)
+                range_box(ra, rb, rn, nbox_lo, nbox_hi);
+            else
+                for (int a = 0; a < 3; ++a) {
+                    nbox_lo[a] = box_lo[a];
+                    nbox_hi[a] = box_hi[a];
+                }
+        }
         // ----- optional refinement inside bin b0 ---------------------------------------------
         const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
         if (__ballot(refine) != 0) {
@@ -510,11 +531,8 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
             for (int w = 0; w < kBinWords; ++w)
                 hist[w * kWave + lane] = 0u;
             __syncthreads();
-            n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
-                          [&](const Pt<T> &c, int pos, int idx) {
-                              if (!refine || pos == q)
-                                  return;
-                              const float f = cull_dist<T, NA>(qp, c);
+            n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, refine,
+                          [&](float f, const Pt<T> &c, int pos, int idx) {
                               if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
                                   return;
                               int sb = (int)((f - base_lo) * s1);
@@ -550,11 +568,8 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
         // ----- pass 2: classify --------------------------------------------------------------
         const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
         int nin = 0, nb = 0;
-        n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
-                      [&](const Pt<T> &c, int pos, int idx) {
-                          if (!act || pos == q)
-                              return;
-                          const float f = cull_dist<T, NA>(qp, c);
+        n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, act,
+                      [&](float f, const Pt<T> &c, int pos, int idx) {
                           if (f * (1.f + e) < lo_t) {
                               if (nin < K)
                                   list[nin * kWave + lane] = idx;
@@ -598,12 +613,9 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
                 double best_k = INFINITY;
                 int best_i = 0x7fffffff, best_p = -1;
                 const bool want = slow && sidx < rr;
-                n_streamed += stream_box<T>(P, g, box_lo, box_hi, lds_rng, lds_stage,
-                              [&](const Pt<T> &c, int pos, int idx) {
-                                  if (!want || pos == q)
-                                      return;
-                                  const float f = cull_dist<T, NA>(qp, c);
-                                  if (f * (1.f + e) < lo_s || f * (1.f - e) > hi_t)
+                n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, want,
+                              [&](float f, const Pt<T> &c, int pos, int idx) {
+                                  if (!(f * (1.f - e) <= hi_t) || f * (1.f + e) < lo_s)
                                       return;
                                   const double k = exact_key<T, NA>(qp, c);
                                   const bool after = k > last_k || (k == last_k && idx > last_i);

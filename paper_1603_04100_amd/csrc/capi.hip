@@ -35,8 +35,9 @@ mvgd_status fail(mvgd_status s, const char *fmt, ...)
     return s;
 }
 
-// Tunables of the neighbour-search grid (cell edge and initial margin relative to the
-// estimated K-th neighbour distance). MVGD_CELL_ALPHA / MVGD_MARGIN_MU override them.
+// Tunables of the neighbour-search grid: cell edge and initial search radius relative to the
+// estimated K-th neighbour distance, and the cell-table budget per point
+// (MVGD_CELL_ALPHA, MVGD_MARGIN_MU, MVGD_CELLS_PER_POINT override them).
 double env_double(const char *name, double dflt)
 {
     const char *v = getenv(name);
@@ -221,7 +222,8 @@ void plan_grid(const double *mn, const double *mx, const double *pmn, const doub
     const double rho = (double)n / area;
     const double dk = std::sqrt((double)K / (M_PI * rho));
     double cell = alpha * dk;
-    const int64_t cap = std::max<int64_t>(4096, next_pow2(4 * n));
+    const double cpp = env_double("MVGD_CELLS_PER_POINT", 8.0);
+    const int64_t cap = std::max<int64_t>(4096, next_pow2((int64_t)(cpp * (double)n)));
     int64_t dim[3];
     for (int it = 0; it < 400; ++it) {
         int64_t total = 1;
