@@ -59,13 +59,13 @@ def make_workload(name: str):
     return clouds.config(name)
 
 
-def run_gpu(mv, torch, P, f, k, steps, warmup, flags):
+def run_gpu(mv, torch, P, f, k, steps, warmup, flags, offsets=None):
     times, tk = [], []
     for it in range(warmup + steps):
         if it == warmup:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-        L = mv.mvgd_assemble(P, k, flags=flags)
+        L = mv.mvgd_assemble(P, k, flags=flags, cloud_offsets=offsets)
         y = mv.mvgd_apply(L, f)
         if it >= warmup:
             tk.append(mv.mvgd_timing(L))
@@ -73,6 +73,19 @@ def run_gpu(mv, torch, P, f, k, steps, warmup, flags):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return wall / steps, tk, y
+
+
+def run_unbatched(mv, torch, P, f, k, offsets, flags):
+    """The same clouds assembled and applied one call per cloud (context for batching)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(len(offsets) - 1):
+        a, b = offsets[c], offsets[c + 1]
+        L = mv.mvgd_assemble(P[a:b], k, flags=flags)
+        mv.mvgd_apply(L, f[a:b].contiguous())
+        mv.mvgd_free(L)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
 
 
 def cpu_baseline(oracle, pts64, k, target_s: float, max_rows: int):
@@ -90,6 +103,36 @@ def cpu_baseline(oracle, pts64, k, target_s: float, max_rows: int):
     return rows, cols, vals, m / dt, dt, m
 
 
+def bench_serving(args):
+    """Serving stream: Poisson arrivals of random spheres / ellipsoids / tori, each request an
+    assemble plus 8 applies; continuous batching (FP32-mixed) against one request at a time
+    (FP64). Prints one JSON line with p50/p99 latency and throughput of both."""
+    import torch
+    from paper_1603_04100_amd import serve
+    reqs = serve.make_requests(duration_s=args.serve_seconds, rate_hz=args.serve_rate, seed=5)
+    print(f"[bench] serving: {len(reqs)} requests over {args.serve_seconds} s at "
+          f"{args.serve_rate}/s, {sum(r.points.shape[0] for r in reqs)} points",
+          file=sys.stderr, flush=True)
+    warm = serve.make_requests(duration_s=0.05, rate_hz=200, seed=99, max_requests=4)
+    serve.Server(precision="fp32").run(warm)
+    serve.one_at_a_time(warm)
+    mixed = serve.Server(precision="fp32", n_streams=4, max_batch=16).run(reqs).summary()
+    print(f"[bench] batched fp32: {mixed}", file=sys.stderr, flush=True)
+    base = serve.one_at_a_time(reqs, precision="fp64").summary()
+    print(f"[bench] one-at-a-time fp64: {base}", file=sys.stderr, flush=True)
+    out = {"metric": "serving p99 latency (assemble + 8 applies per request)",
+           "value": mixed["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": mixed["requests"],
+           "warmup": 4, "ms_per_step": mixed["mean_ms"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage/f64 solves",
+           "data": "synthetic",
+           "config": {"workload": "serving", "rate_hz": args.serve_rate,
+                      "duration_s": args.serve_seconds, "k": 24, "n_apply": 8,
+                      "sizes": "log-uniform [5e3, 5e5]", "noise": 1e-3},
+           "batched_fp32": mixed, "one_at_a_time_fp64": base,
+           "kernel_source_hash": kernel_source_hash()}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +142,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy per step (counter scaling reference)")
     args = ap.parse_args()
@@ -110,12 +155,19 @@ def main():
     import torch
     from paper_1603_04100_amd import mvgd as mv
 
+    if args.workload == "serving":
+        return bench_serving(args)
     cl = make_workload(args.workload)
     n, k = cl.n_points, cl.k
+    batched = cl.offsets.shape[0] > 2
+    offsets = [int(v) for v in cl.offsets] if batched else None
+    nrhs = cl.f.shape[1] if batched else 1
     dev = "cuda:0"
     pts32 = cl.points.astype(np.float32)
     P32 = torch.tensor(pts32, device=dev)
-    f32 = torch.tensor(cl.f[:, 0].astype(np.float32), device=dev)
+    f32 = torch.tensor(np.ascontiguousarray(cl.f[:, :nrhs].astype(np.float32)), device=dev)
+    if nrhs == 1:
+        f32 = f32.reshape(-1)
     print(f"[bench] {args.workload}: N={n} K={k} n={cl.n_ambient}; warmup {args.warmup}, "
           f"steps {args.steps}", file=sys.stderr, flush=True)
     if args.copy_probe:
@@ -123,7 +175,8 @@ def main():
         b = torch.empty_like(a)
     flags = mv.MVGD_FLAG_TIME
     # ---------------- FP32-mixed (headline) ----------------
-    t32, tk32, y32 = run_gpu(mv, torch, P32, f32, k, args.steps, args.warmup, flags)
+    t32, tk32, y32 = run_gpu(mv, torch, P32, f32, k, args.steps, args.warmup, flags, offsets)
+    unbatched = run_unbatched(mv, torch, P32, f32, k, offsets, 0) if batched else None
     if args.copy_probe:
         for _ in range(args.steps):
             b.copy_(a)
@@ -135,7 +188,7 @@ def main():
           f"{asm32:.3f}, apply {app32:.3f} ms)", file=sys.stderr, flush=True)
     # ---------------- FP64 on the same GPU ----------------
     fp64 = None
-    if not args.no_fp64:
+    if not args.no_fp64 and not batched:
         P64 = torch.tensor(cl.points, device=dev)
         f64 = torch.tensor(cl.f[:, 0], device=dev)
         st64 = max(3, args.steps // 2)
@@ -151,23 +204,28 @@ def main():
 
     # ---------------- accuracy against the FP64 oracle + CPU baseline ----------------
     acc, cpu = {}, None
-    y32n = y32.cpu().numpy().astype(np.float64)
+    y32n = y32.cpu().numpy().astype(np.float64).reshape(n, -1)[:, 0]
     acc["max_abs_lf_minus_exact_fp32"] = float(np.abs(y32n - cl.lap_f[:, 0]).max())
     acc["rms_lf_minus_exact_fp32"] = float(np.sqrt(((y32n - cl.lap_f[:, 0]) ** 2).mean()))
     if not args.no_cpu_baseline:
         import oracle
-        pts_o = pts32.astype(np.float64)  # the FP32-mixed run's exact input
+        # the sampled cloud: the whole cloud, or the largest cloud of a batch
+        c = int(np.argmax(np.diff(cl.offsets))) if batched else 0
+        a, b = int(cl.offsets[c]), int(cl.offsets[c + 1])
+        pts_o = pts32[a:b].astype(np.float64)  # the FP32-mixed run's exact input
         rows, ocols, ovals, rps, dt, m = cpu_baseline(oracle, pts_o, k, args.cpu_seconds, 200_000)
         cpu = {"value": rps, "unit": "rows/s", "cores": oracle.threads(), "kind": "oracle",
-               "sample": f"{m} random rows of the same {n}-point cloud (FP64 oracle: brute-force "
-                         f"kNN over all {n} points + Householder QR per row), {dt:.1f} s wall"}
+               "sample": f"{m} random rows of a {b - a}-point cloud of the workload (FP64 oracle: "
+                         f"brute-force kNN over all {b - a} points + Householder QR per row), "
+                         f"{dt:.1f} s wall"}
         # row parity of the GPU matrix on the sampled rows and L.f error vs the FP64 oracle
-        L = mv.mvgd_assemble(P32, k)
+        L = mv.mvgd_assemble(P32, k, cloud_offsets=offsets)
         rp, col, val = mv.mvgd_csr(L)
-        col = col.cpu().numpy().reshape(n, k + 1)[rows]
-        val = val.cpu().numpy().astype(np.float64).reshape(n, k + 1)[rows]
+        col = col.cpu().numpy().reshape(n, k + 1)[a:b][rows]
+        val = val.cpu().numpy().astype(np.float64).reshape(n, k + 1)[a:b][rows]
         mv.mvgd_free(L)
-        ref = (ovals * cl.f[ocols, 0]).sum(1)
+        ref = (ovals * cl.f[a:b][ocols, 0]).sum(1)
+        y32n = y32n[a:b]
         acc["sampled_rows"] = int(m)
         acc["knn_sparsity_identical"] = bool((col == ocols).all())
         acc["max_row_rel_err_fp32"] = float((np.abs(val - ovals).max(1) / np.abs(ovals).max(1)).max())
@@ -176,6 +234,9 @@ def main():
     # ---------------- roofline of the dominant kernel ----------------
     s_p, s_v = 4, 4
     bytes_per_row = cl.n_ambient * s_p + (k + 1) * (4 + s_v)
+    metric = ("MVGD rows/s at N=1M (FP32-mixed vs FP64), L·f rel err vs FP64 oracle; p99 ms"
+              if not batched else
+              "MVGD rows/s, batched assembly of many clouds in one launch + apply of 4 RHS")
     achieved = bytes_per_row * n / (asm32 * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -183,13 +244,15 @@ def main():
             "kernel": "assemble_kernel<float,4>", "kernel_ms": round(asm32, 4),
             "algorithmic_bytes_per_row": bytes_per_row}
     out = {
-        "metric": "MVGD rows/s at N=1M (FP32-mixed vs FP64), L·f rel err vs FP64 oracle; p99 ms",
+        "metric": metric,
         "value": n / t32, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": t32 * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage/f64 solves",
         "data": "synthetic",
         "config": {"workload": args.workload, "n_points": n, "k": k, "n_ambient": cl.n_ambient,
-                   "precision": "fp32-mixed", "nrhs": 1, "step": "assemble+apply"},
+                   "precision": "fp32-mixed", "nrhs": nrhs, "step": "assemble+apply",
+                   "n_clouds": int(cl.offsets.shape[0] - 1)},
+        "unbatched_ms": None if unbatched is None else unbatched * 1e3,
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": fp64,

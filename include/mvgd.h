@@ -66,7 +66,19 @@ typedef struct {
     int32_t precision;  /* mvgd_precision */
     uint32_t flags;     /* MVGD_FLAG_* */
     double h_override;  /* > 0, used only with MVGD_FLAG_H_OVERRIDE */
+    /* Neighbour-search tuning (performance only: results do not depend on it). 0 selects the
+     * built-in default. Values come from the autotuner (paper_1603_04100_amd/autotune.py). */
+    float cell_alpha;      /* grid cell edge / estimated K-th neighbour distance (0.6)        */
+    float radius_mu;       /* initial search radius / estimated K-th neighbour distance (1.7) */
+    float cells_per_point; /* cell-table entries budgeted per point (8)                       */
+    int32_t launch;        /* MVGD_LAUNCH_*                                                   */
 } mvgd_params;
+
+enum {
+    MVGD_LAUNCH_DEFAULT = 0,
+    MVGD_LAUNCH_GRID = 1,      /* one workgroup per 64-point group, XCD-aware order */
+    MVGD_LAUNCH_PERSISTENT = 2 /* resident workgroups popping groups from per-XCD queues */
+};
 
 typedef struct {
     int64_t n_rows;        /* rows = points over all clouds */

@@ -51,6 +51,7 @@ struct AsmParams {
     void *ell_val;              // [K+1][ld] weights (T)
     double *row_h;              // optional, sorted order
     uint8_t *row_flags;         // optional, sorted order
+    unsigned int *queue;          // [8] per-XCD work-queue counters (persistent launch)
     unsigned long long *counters; // [0] degenerate rows, [1] slow-path rows, [2] internal errors,
                                   // [3] sub-groups, [4] candidates streamed, [5] radius growths
 };
@@ -329,10 +330,9 @@ __device__ __forceinline__ void monomials(T xi, T eta, double m[6])
 // the kernel
 // ---------------------------------------------------------------------------------------------
 template <typename T, int NA>
-__global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
+__device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t group, char *lds)
 {
     constexpr int NC = NA - 2; // normal coordinates
-    extern __shared__ __attribute__((aligned(16))) char lds[];
     const int lane = lane_id();
     const int K = P.K;
     char *lds_rng = lds + kLdsList + K * kWave * 4;
@@ -342,11 +342,6 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
     int32_t *bndpos = (int32_t *)(lds + kLdsBndPos);
     int32_t *list = (int32_t *)(lds + kLdsList);
 
-    // XCD-aware remap: consecutive groups (neighbouring space) go to the same XCD / L2.
-    const int64_t b = blockIdx.x;
-    const int64_t group = (b & 7) * P.groups_per_xcd + (b >> 3);
-    if (group >= P.n_groups)
-        return;
     int ci = 0;
     {
         int lo = 0, hi = P.n_clouds - 1;
@@ -961,6 +956,48 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
             atomicAdd(&P.counters[0], nd);
         if (ns)
             atomicAdd(&P.counters[1], ns);
+    }
+}
+
+// Grid-mapped launch: one workgroup per group, XCD-aware remap (workgroups are dispatched to the
+// eight XCDs round-robin, so workgroup b runs on XCD b % 8; consecutive groups, which are
+// neighbours in space, go to the same XCD and share its L2).
+template <typename T, int NA>
+__global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int64_t b = blockIdx.x;
+    const int64_t group = (b & 7) * P.groups_per_xcd + (b >> 3);
+    if (group >= P.n_groups)
+        return;
+    assemble_group<T, NA>(P, group, lds);
+}
+
+// Persistent launch: as many workgroups as fit on the device at once; each pops groups from the
+// queue of its XCD (queue x owns groups [x * groups_per_xcd, (x + 1) * groups_per_xcd)) and,
+// when that queue is empty, steals from the others in turn. Every workgroup exits once all eight
+// queues are exhausted. The queue counters must be zero at launch.
+template <typename T, int NA>
+__global__ __launch_bounds__(64) void assemble_persistent_kernel(AsmParams P)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const int home = (int)(blockIdx.x & 7);
+    for (int v = 0; v < 8; ++v) {
+        const int qx = (home + v) & 7;
+        const int64_t base = (int64_t)qx * P.groups_per_xcd;
+        const int64_t len = min(P.groups_per_xcd, P.n_groups - base);
+        if (len <= 0)
+            continue;
+        for (;;) {
+            unsigned int t = 0;
+            if (lane_id() == 0)
+                t = atomicAdd(&P.queue[qx], 1u);
+            t = (unsigned int)uniform((int)t);
+            if ((int64_t)t >= len)
+                break;
+            assemble_group<T, NA>(P, base + t, lds);
+            __syncthreads();
+        }
     }
 }
 

@@ -35,17 +35,14 @@ mvgd_status fail(mvgd_status s, const char *fmt, ...)
     return s;
 }
 
-// Tunables of the neighbour-search grid: cell edge and initial search radius relative to the
-// estimated K-th neighbour distance, and the cell-table budget per point
-// (MVGD_CELL_ALPHA, MVGD_MARGIN_MU, MVGD_CELLS_PER_POINT override them).
-double env_double(const char *name, double dflt)
+// Neighbour-search tunables (mvgd_params; 0 selects these defaults).
+constexpr double kDefaultCellAlpha = 0.6;
+constexpr double kDefaultRadiusMu = 1.7;
+constexpr double kDefaultCellsPerPoint = 8.0;
+
+double tunable(float v, double dflt)
 {
-    const char *v = getenv(name);
-    if (!v || !*v)
-        return dflt;
-    char *end = nullptr;
-    double x = strtod(v, &end);
-    return (end && end != v && std::isfinite(x) && x > 0) ? x : dflt;
+    return (v > 0.0f && std::isfinite(v)) ? (double)v : dflt;
 }
 
 // Allocation with an optional injected failure, to exercise the clean-up paths:
@@ -204,10 +201,11 @@ Proj binning_projection(int n_amb)
 // cell edge follows the estimated K-th neighbour distance of a surface sample: the area of a
 // closed surface is taken as about half the surface of its projected bounding box.
 void plan_grid(const double *mn, const double *mx, const double *pmn, const double *pmx,
-               const Proj &pr, int n_amb, int64_t n, int K, int64_t row0, HostGrid &hg)
+               const Proj &pr, int n_amb, int64_t n, int K, int64_t row0, const mvgd_params &prm,
+               HostGrid &hg)
 {
-    const double alpha = env_double("MVGD_CELL_ALPHA", 0.6);
-    const double mu = env_double("MVGD_MARGIN_MU", 1.7);
+    const double alpha = tunable(prm.cell_alpha, kDefaultCellAlpha);
+    const double mu = tunable(prm.radius_mu, kDefaultRadiusMu);
     double diam2 = 0.0;
     for (int a = 0; a < n_amb; ++a)
         diam2 += (mx[a] - mn[a]) * (mx[a] - mn[a]);
@@ -222,7 +220,7 @@ void plan_grid(const double *mn, const double *mx, const double *pmn, const doub
     const double rho = (double)n / area;
     const double dk = std::sqrt((double)K / (M_PI * rho));
     double cell = alpha * dk;
-    const double cpp = env_double("MVGD_CELLS_PER_POINT", 8.0);
+    const double cpp = tunable(prm.cells_per_point, kDefaultCellsPerPoint);
     const int64_t cap = std::max<int64_t>(4096, next_pow2((int64_t)(cpp * (double)n)));
     int64_t dim[3];
     for (int it = 0; it < 400; ++it) {
@@ -384,7 +382,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
             pmx[a] = decode(hs[c].pmx[a]);
         }
         const int64_t n = offs[c + 1] - offs[c];
-        plan_grid(mn, mx, pmn, pmx, proj, n_amb, n, K, offs[c], hg[c]);
+        plan_grid(mn, mx, pmn, pmx, proj, n_amb, n, K, offs[c], p, hg[c]);
         CloudGrid &g = hg[c].g;
         g.cell0 = cell_total;
         g.group0 = group_total;
@@ -408,6 +406,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     MVGD_ALLOC(d_keys, sizeof(uint32_t) * n_total, "keys");
     MVGD_ALLOC(d_slots, sizeof(uint32_t) * n_total, "slots");
     MVGD_ALLOC(d_spts, sizeof(Pt<T>) * n_total, "sorted points");
+    unsigned int *d_queue;
+    MVGD_ALLOC(d_queue, sizeof(unsigned int) * 8, "work queues");
     int32_t *d_iperm;
     MVGD_ALLOC(d_iperm, sizeof(int32_t) * n_total, "inverse permutation");
     // scan levels
@@ -498,14 +498,34 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.row_h = L->row_h;
     ap.row_flags = L->row_flags;
     ap.counters = L->counters;
+    ap.queue = d_queue;
     const size_t lds = (size_t)lds_bytes(K, (int)sizeof(Pt<T>));
-    const unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
+    const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
+    unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
+    if (persistent) {
+        int per_cu = 0, n_cu = 0;
+        auto kern = n_amb == 3 ? assemble_persistent_kernel<T, 3> : assemble_persistent_kernel<T, 4>;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+            return fail(MVGD_EDEVICE, "occupancy query failed");
+        const int64_t resident = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
+        nblk = (unsigned)std::min<int64_t>((resident + 7) / 8 * 8, ap.groups_per_xcd * 8);
+        if (hipMemsetAsync(d_queue, 0, sizeof(unsigned int) * 8, stream) != hipSuccess)
+            return fail(MVGD_EDEVICE, "queue reset failed");
+    }
     if (L->ev[1])
         (void)hipEventRecord(L->ev[1], stream);
-    if (n_amb == 3)
-        assemble_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
-    else
-        assemble_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
+    if (persistent) {
+        if (n_amb == 3)
+            assemble_persistent_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
+        else
+            assemble_persistent_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
+    } else {
+        if (n_amb == 3)
+            assemble_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
+        else
+            assemble_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
+    }
     if (mvgd_status st = check_launch("assemble"); st != MVGD_OK)
         return st;
     if (L->ev[2])
@@ -541,6 +561,13 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
         return fail(MVGD_EINVAL, "unknown flag bits 0x%x", p->flags);
     if ((p->flags & MVGD_FLAG_H_OVERRIDE) && !(p->h_override > 0.0 && std::isfinite(p->h_override)))
         return fail(MVGD_EINVAL, "h_override must be positive and finite");
+    if (p->launch < MVGD_LAUNCH_DEFAULT || p->launch > MVGD_LAUNCH_PERSISTENT)
+        return fail(MVGD_EINVAL, "unknown launch mode %d", p->launch);
+    if (p->cell_alpha < 0.0f || p->radius_mu < 0.0f || p->cells_per_point < 0.0f ||
+        !std::isfinite(p->cell_alpha) || !std::isfinite(p->radius_mu) ||
+        !std::isfinite(p->cells_per_point) || (p->cells_per_point > 0.0f && p->cells_per_point < 0.25f) ||
+        p->cells_per_point > 64.0f || (p->radius_mu > 0.0f && p->radius_mu < 0.1f))
+        return fail(MVGD_EINVAL, "tuning values out of range");
     if (n_total <= 0 || n_total >= (int64_t(1) << 31))
         return fail(MVGD_EINVAL, "n_total must be in [1, 2^31)");
     if (cloud_offsets) {

@@ -36,7 +36,12 @@ class MvgdError(RuntimeError):
 class mvgd_params(ctypes.Structure):
     _fields_ = [("n_ambient", ctypes.c_int32), ("d_manifold", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("flags", ctypes.c_uint32), ("h_override", ctypes.c_double)]
+                ("flags", ctypes.c_uint32), ("h_override", ctypes.c_double),
+                ("cell_alpha", ctypes.c_float), ("radius_mu", ctypes.c_float),
+                ("cells_per_point", ctypes.c_float), ("launch", ctypes.c_int32)]
+
+
+MVGD_LAUNCH_DEFAULT, MVGD_LAUNCH_GRID, MVGD_LAUNCH_PERSISTENT = 0, 1, 2
 
 
 class mvgd_info_t(ctypes.Structure):
@@ -124,8 +129,12 @@ class Matrix:
 
 def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision=None,
                   flags: int = 0, h_override: float | None = None, d_manifold: int = 2,
-                  stream=None) -> Matrix:
-    """Assemble L from device points [N, n] (float32 -> FP32-mixed, float64 -> FP64)."""
+                  tuning: dict | None = None, stream=None) -> Matrix:
+    """Assemble L from device points [N, n] (float32 -> FP32-mixed, float64 -> FP64).
+
+    tuning: neighbour-search tunables {cell_alpha, radius_mu, cells_per_point, launch}; by
+    default the autotuner's table (tuning.json) is consulted for this shape.
+    """
     if not isinstance(points, torch.Tensor) or points.dim() != 2:
         raise ValueError("points must be a 2-D torch tensor")
     if precision is None:
@@ -138,7 +147,15 @@ def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision
         raise ValueError("points must be contiguous")
     if h_override is not None:
         flags |= MVGD_FLAG_H_OVERRIDE
-    p = mvgd_params(points.shape[1], d_manifold, k, prec, flags, float(h_override or 0.0))
+    if tuning is None:
+        from . import autotune
+        tuning = autotune.lookup(points.shape[1], k, precision,
+                                 points.shape[0] if cloud_offsets is None
+                                 else points.shape[0] // max(1, len(cloud_offsets) - 1))
+    t = tuning or {}
+    p = mvgd_params(points.shape[1], d_manifold, k, prec, flags, float(h_override or 0.0),
+                    float(t.get("cell_alpha", 0.0)), float(t.get("radius_mu", 0.0)),
+                    float(t.get("cells_per_point", 0.0)), int(t.get("launch", 0)))
     offs_ptr, n_clouds = None, 1
     if cloud_offsets is not None:
         offs = (ctypes.c_int64 * len(cloud_offsets))(*[int(v) for v in cloud_offsets])

@@ -327,3 +327,60 @@ def test_allocation_failure_cleans_up(mv):
     assert torch.equal(c2, cc) and torch.equal(v2, vc)
     L.free()
     ref.free()
+
+
+# ----------------------------------------------------------------------------------------------
+# launch modes and tuning change only performance: results are bit-identical
+# ----------------------------------------------------------------------------------------------
+def test_launch_modes_and_tuning_do_not_change_results(mv):
+    cl = clouds.ellipsoid_batch(n_clouds=5, seed=13, k=20, n_min=300, n_max=20000)
+    P = torch.tensor(cl.points.astype(np.float32), device=DEV)
+    offs = [int(v) for v in cl.offsets]
+    ref = None
+    for tuning in ({"launch": 1}, {"launch": 2},
+                   {"launch": 2, "cell_alpha": 1.0, "radius_mu": 1.4, "cells_per_point": 4.0},
+                   {"launch": 1, "cell_alpha": 0.45, "radius_mu": 2.0, "cells_per_point": 16.0}):
+        L = mv.mvgd_assemble(P, 20, cloud_offsets=offs, tuning=tuning)
+        rp, col, val = mv.mvgd_csr(L)
+        y = mv.mvgd_apply(L, torch.tensor(cl.f.astype(np.float32), device=DEV))
+        out = (col.cpu().numpy(), val.cpu().numpy(), y.cpu().numpy())
+        L.free()
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(ref, out):
+                assert (a == b).all(), tuning
+
+
+# ----------------------------------------------------------------------------------------------
+# serving: results are the same alone and in the mix; admission under a tiny HBM budget
+# ----------------------------------------------------------------------------------------------
+def test_serving_alone_equals_mixed():
+    from paper_1603_04100_amd import serve
+    reqs = serve.make_requests(duration_s=0.1, rate_hz=300, seed=11, k=24, n_min=2000,
+                               n_max=20000, n_apply=8, max_requests=24)
+    assert len(reqs) >= 10
+    mixed = serve.Server(precision="fp32", n_streams=3, max_batch=8).run(reqs, batching=True)
+    got = {r.id: r.result.copy() for r in reqs}
+    assert mixed.summary()["requests"] == len(reqs) and max(mixed.batch_sizes) > 1
+    alone = serve.Server(precision="fp32", n_streams=1, max_batch=1).run(reqs, batching=False)
+    for r in reqs:
+        assert (r.result == got[r.id]).all(), r.id
+    # each result is L f of its own cloud: compare with the oracle on the first few requests
+    for r in reqs[:3]:
+        pts = r.points.astype(np.float32).astype(np.float64)
+        oc, ov = oracle.rows(pts, r.k)
+        ref = np.stack([(ov * r.rhs.astype(np.float32).astype(np.float64)[oc, j]).sum(1)
+                        for j in range(r.rhs.shape[1])], 1)
+        assert np.abs(r.result - ref).max() <= 1e-3 * np.abs(ref).max()
+    print(f"\n[serving] mixed {mixed.summary()}\n[serving] alone {alone.summary()}")
+
+
+def test_serving_admission_with_tiny_budget():
+    from paper_1603_04100_amd import serve
+    reqs = serve.make_requests(duration_s=0.05, rate_hz=400, seed=12, k=24, n_min=3000,
+                               n_max=6000, max_requests=8)
+    budget = serve.footprint_bytes(6000, 3, 24, 8, 4) + 1
+    st = serve.Server(precision="fp32", n_streams=4, max_batch=8, hbm_budget_bytes=budget).run(reqs)
+    assert st.summary()["requests"] == len(reqs)
+    assert st.admission_waits > 0 and max(st.batch_sizes) == 1
