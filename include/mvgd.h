@@ -8,7 +8,7 @@
  * K nearest neighbours, so that (L U)_i approximates the Laplace-Beltrami operator of U at p_i
  * (Sec. 2, problem statement and the assembled matrix A; Sec. 3.1, the MVGD). mvgd_apply computes
  * y = L x. All work runs in HIP kernels on the device; the host only validates arguments, sizes
- * the cell grids and enqueues work.
+ * the buffers and enqueues work.
  *
  * Conventions shared by every entry point:
  *  - Plain pointers and sizes only. Device buffers are device-resident memory (hipMalloc,
@@ -119,11 +119,11 @@ typedef struct {
  * stream        hipStream_t as void*.
  * out           receives the handle on MVGD_OK, NULL otherwise.
  *
- * Synchronisation: after one reduction over the input (bounding box and finiteness per cloud) the
- * call waits for `stream` once, so that it can reject non-finite input synchronously and size the
- * cell grids exactly; all remaining work is enqueued on `stream` and the call returns without
- * waiting for it. The handle may be used on `stream` at once, or on another stream after the
- * caller has ordered that stream after `stream`.
+ * Synchronisation: the bounding boxes, the cell grids (planned on the device from the boxes)
+ * and the binning are enqueued first; the call then waits for `stream` once, so that it can reject
+ * non-finite input synchronously before the neighbour search. The search and the stencils are
+ * enqueued on `stream` and the call returns without waiting for them. The handle may be used on
+ * `stream` at once, or on another stream after the caller has ordered that stream after `stream`.
  */
 mvgd_status mvgd_assemble(const void *points, int64_t n_total, const int64_t *cloud_offsets,
                           int32_t n_clouds, const mvgd_params *p, void *stream,
@@ -175,7 +175,8 @@ typedef struct {
 } mvgd_timing_t;
 
 /* mvgd_timing -- device durations measured with HIP events on the stream each call was enqueued
- * on; needs MVGD_FLAG_TIME at assembly, otherwise MVGD_EINVAL. Waits for the handle's stream. */
+ * on; needs MVGD_FLAG_TIME at assembly, otherwise MVGD_EINVAL. Waits for the handle's last
+ * recorded event only (work enqueued on the stream after it is not waited for). */
 mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t);
 
 /* mvgd_info -- sizes and counters; waits for the handle's stream (synchronous). */

@@ -1,6 +1,7 @@
 // bin.hpp -- counting sort of the points into Morton-ordered cells (the neighbour-search grid).
 //
 // bbox_kernel      per-cloud bounding box over all ambient coordinates + non-finite count
+// plan_kernel      per-cloud cell grid and Morton part tables from the bounding boxes
 // key_kernel       cell key of every point and its slot inside the cell (atomic count)
 // scan_*           exclusive prefix sum of the cell counts -> cell start offsets
 // scatter_kernel   cell-sorted copy of the points (padded to 4 components), permutation and
@@ -20,9 +21,15 @@ struct CloudStats {  // ordered-encoded doubles; see ord_encode
     unsigned long long pad;
 };
 
-__global__ void stats_init_kernel(CloudStats *st, int n_clouds)
+// Resets the per-cloud statistics, the search counters and the work-queue heads.
+__global__ void stats_init_kernel(CloudStats *st, int n_clouds, unsigned long long *counters,
+                                  unsigned int *queue)
 {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < 8) {
+        counters[c] = 0;
+        queue[c] = 0;
+    }
     if (c >= n_clouds)
         return;
     for (int a = 0; a < 4; ++a) {
@@ -164,6 +171,139 @@ __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts,
         spts[pos] = p;
         perm[pos] = (int32_t)i;
         iperm[i] = (int32_t)pos;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// grid planning on the device (one block per cloud), straight from the bounding boxes
+// ---------------------------------------------------------------------------------------------
+constexpr int kMaxDim = 1024; // cells per projected axis
+
+// Per-cloud layout of the metadata array (int64, host-computed, uploaded once per call):
+// [0, n]      row offsets (n + 1 entries)
+// then n entries each of: first cell-table entry, cell budget, first 64-point group, first
+// Morton part-table entry.
+struct PlanArgs {
+    const CloudStats *stats;
+    const int64_t *meta;
+    int32_t n_clouds;
+    int32_t n_amb;
+    int32_t K;
+    int32_t pad;
+    double alpha;          // cell edge / estimated K-th neighbour distance
+    double mu;             // initial search radius / estimated K-th neighbour distance
+    Proj proj;
+    CloudGrid *grids;
+    uint32_t *parts;
+};
+
+__device__ __forceinline__ double ord_decode(unsigned long long u)
+{
+    const unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
+    return __longlong_as_double((long long)b);
+}
+
+// Cell edge from the estimated K-th neighbour distance of a surface sample (the area of a closed
+// surface is taken as about half the surface of its projected bounding box), coarsened until the
+// power-of-two grid fits the cloud's cell budget; Morton part tables interleave the bits of the
+// three cell coordinates (axes with fewer bits drop out of the higher levels).
+__global__ __launch_bounds__(256) void plan_kernel(PlanArgs a)
+{
+    const int c = blockIdx.x;
+    __shared__ int32_t dim_s[3];
+    __shared__ int32_t pos_s[3][16];
+    __shared__ int64_t part0_s;
+    if (threadIdx.x == 0) {
+        const CloudStats st = a.stats[c];
+        const int64_t *m = a.meta + a.n_clouds + 1;
+        const int64_t row0 = a.meta[c], n = a.meta[c + 1] - a.meta[c];
+        const int64_t cell0 = m[c], cap = m[a.n_clouds + c];
+        double diam2 = 0.0;
+        for (int k = 0; k < a.n_amb; ++k) {
+            const double e = ord_decode(st.mx[k]) - ord_decode(st.mn[k]);
+            diam2 += e * e;
+        }
+        double Eb[3], lo[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = ord_decode(st.pmn[k]);
+            Eb[k] = ord_decode(st.pmx[k]) - lo[k];
+        }
+        const double emax = fmax(fmax(Eb[0], fmax(Eb[1], Eb[2])), 1e-300);
+        double Ef[3];
+        for (int k = 0; k < 3; ++k)
+            Ef[k] = fmax(Eb[k], emax * 1e-3);
+        const double area = 0.55 * 2.0 * (Ef[0] * Ef[1] + Ef[1] * Ef[2] + Ef[0] * Ef[2]);
+        double dk = sqrt((double)a.K * area / (M_PI * (double)n));
+        if (!(dk > 0.0 && dk < 1e300)) // extent below the double range, or no finite point
+            dk = (emax > 1e-300 && emax < 1e300) ? emax : 1.0;
+        double cell = a.alpha * dk;
+        int dim[3] = {1, 1, 1};
+        bool fits = false;
+        for (int it = 0; it < 400 && !fits; ++it) {
+            int64_t total = 1;
+            bool ok = true;
+            for (int k = 0; k < 3; ++k) {
+                double cnt = floor(Eb[k] / cell) + 1.0;
+                if (!(cnt <= (double)kMaxDim)) {
+                    ok = false;
+                    cnt = (double)kMaxDim;
+                }
+                int d = 1;
+                while (d < (int)cnt)
+                    d <<= 1;
+                dim[k] = d;
+                total *= d;
+            }
+            fits = ok && total <= cap;
+            if (!fits)
+                cell *= 1.26;
+        }
+        if (!fits) { // a single cell (the search then scans the whole cloud)
+            dim[0] = dim[1] = dim[2] = 1;
+            cell = fmax(emax, 1e-300);
+        }
+        CloudGrid g;
+        memset(&g, 0, sizeof g);
+        g.row0 = row0;
+        g.n = n;
+        g.cell0 = cell0;
+        g.group0 = m[2 * a.n_clouds + c];
+        g.part0 = m[3 * a.n_clouds + c];
+        g.proj = a.proj;
+        for (int k = 0; k < 3; ++k) {
+            g.lo[k] = lo[k];
+            g.dim[k] = dim[k];
+        }
+        g.cell = cell;
+        g.inv_cell = 1.0 / cell;
+        g.diam2 = diam2;
+        g.r0 = fmax(a.mu * dk, 0.5 * cell); // positive, so that radius growth reaches the box
+        a.grids[c] = g;
+        part0_s = g.part0;
+        int bits[3], maxb = 0;
+        for (int k = 0; k < 3; ++k) {
+            bits[k] = 0;
+            while ((1 << bits[k]) < dim[k])
+                ++bits[k];
+            maxb = bits[k] > maxb ? bits[k] : maxb;
+        }
+        int p = 0;
+        for (int l = 0; l < maxb; ++l)
+            for (int k = 0; k < 3; ++k)
+                if (l < bits[k])
+                    pos_s[k][l] = p++;
+        for (int k = 0; k < 3; ++k)
+            dim_s[k] = dim[k];
+    }
+    __syncthreads();
+    const int total = dim_s[0] + dim_s[1] + dim_s[2];
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+        const int k = t < dim_s[0] ? 0 : (t < dim_s[0] + dim_s[1] ? 1 : 2);
+        const int x = t - (k == 0 ? 0 : (k == 1 ? dim_s[0] : dim_s[0] + dim_s[1]));
+        uint32_t code = 0;
+        for (int l = 0; (1 << l) < dim_s[k]; ++l)
+            code |= (uint32_t)((x >> l) & 1) << pos_s[k][l];
+        a.parts[part0_s + t] = code;
     }
 }
 

@@ -72,41 +72,12 @@ hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s)
     return hipMallocAsync(p, bytes, s);
 }
 
-struct ScratchList {
-    std::vector<void *> ptrs;
-    hipStream_t s = nullptr;
-    ~ScratchList()
-    {
-        for (void *p : ptrs)
-            if (p)
-                (void)hipFreeAsync(p, s);
-    }
-    template <typename P>
-    hipError_t alloc(P **p, size_t bytes)
-    {
-        void *v = nullptr;
-        hipError_t e = dev_alloc(&v, bytes, s);
-        if (e == hipSuccess)
-            ptrs.push_back(v);
-        *p = (P *)v;
-        return e;
-    }
-};
-
 int64_t next_pow2(int64_t v)
 {
     int64_t p = 1;
     while (p < v)
         p <<= 1;
     return p;
-}
-
-int ilog2(int64_t v)
-{
-    int b = 0;
-    while ((int64_t(1) << b) < v)
-        ++b;
-    return b;
 }
 
 mvgd_status check_launch(const char *what)
@@ -143,6 +114,7 @@ struct mvgd_matrix {
     int32_t n_clouds = 0;
     int64_t ld = 0;
     hipStream_t stream = nullptr; // stream of the last call on this handle
+    void *block = nullptr;        // one device allocation holding every array below but xs
     int32_t *perm = nullptr;
     int32_t *ell_col = nullptr;
     void *ell_val = nullptr;
@@ -163,7 +135,7 @@ void release(mvgd_matrix *L)
 {
     if (!L)
         return;
-    void *ptrs[] = {L->perm, L->ell_col, L->ell_val, L->grids, L->counters, L->row_h, L->row_flags, L->xs};
+    void *ptrs[] = {L->block, L->xs};
     for (void *p : ptrs)
         if (p)
             (void)hipFreeAsync(p, L->stream);
@@ -172,11 +144,6 @@ void release(mvgd_matrix *L)
             (void)hipEventDestroy(e);
     delete L;
 }
-
-struct HostGrid {
-    CloudGrid g;
-    std::vector<uint32_t> parts;
-};
 
 // The fixed binning projection (rows orthonormal): identity for n = 3, a generic 3x4 matrix for
 // n = 4 (see Proj in common.hpp).
@@ -197,85 +164,67 @@ Proj binning_projection(int n_amb)
     return pr;
 }
 
-// Cell grid of one cloud from its bounding boxes (ambient: diameter; projected: the grid). The
-// cell edge follows the estimated K-th neighbour distance of a surface sample: the area of a
-// closed surface is taken as about half the surface of its projected bounding box.
-void plan_grid(const double *mn, const double *mx, const double *pmn, const double *pmx,
-               const Proj &pr, int n_amb, int64_t n, int K, int64_t row0, const mvgd_params &prm,
-               HostGrid &hg)
+// Cell-table budget of one cloud (entries): a power of two, at least cells_per_point per point.
+int64_t cell_budget(int64_t n, double cpp)
 {
-    const double alpha = tunable(prm.cell_alpha, kDefaultCellAlpha);
-    const double mu = tunable(prm.radius_mu, kDefaultRadiusMu);
-    double diam2 = 0.0;
-    for (int a = 0; a < n_amb; ++a)
-        diam2 += (mx[a] - mn[a]) * (mx[a] - mn[a]);
-    double Eb[3];
-    for (int a = 0; a < 3; ++a)
-        Eb[a] = pmx[a] - pmn[a];
-    const double emax = std::max(std::max(Eb[0], std::max(Eb[1], Eb[2])), 1e-300);
-    double Ef[3];
-    for (int a = 0; a < 3; ++a)
-        Ef[a] = std::max(Eb[a], emax * 1e-3);
-    const double area = 0.55 * 2.0 * (Ef[0] * Ef[1] + Ef[1] * Ef[2] + Ef[0] * Ef[2]);
-    const double rho = (double)n / area;
-    const double dk = std::sqrt((double)K / (M_PI * rho));
-    double cell = alpha * dk;
-    const double cpp = tunable(prm.cells_per_point, kDefaultCellsPerPoint);
-    const int64_t cap = std::max<int64_t>(4096, next_pow2((int64_t)(cpp * (double)n)));
-    int64_t dim[3];
-    for (int it = 0; it < 400; ++it) {
-        int64_t total = 1;
-        bool ok = true;
-        for (int a = 0; a < 3; ++a) {
-            double cnt = std::floor(Eb[a] / cell) + 1.0;
-            if (!(cnt <= 1024.0)) {
-                ok = false;
-                cnt = 1024.0;
-            }
-            dim[a] = next_pow2((int64_t)cnt);
-            total *= dim[a];
-        }
-        if (ok && total <= cap)
-            break;
-        cell *= 1.26;
-    }
-    CloudGrid &g = hg.g;
-    memset(&g, 0, sizeof g);
-    g.row0 = row0;
-    g.n = n;
-    g.proj = pr;
-    for (int a = 0; a < 3; ++a) {
-        g.lo[a] = pmn[a];
-        g.dim[a] = (int32_t)dim[a];
-    }
-    g.cell = cell;
-    g.inv_cell = 1.0 / cell;
-    g.diam2 = diam2;
-    g.r0 = mu * dk;
-    // Morton part tables: bit l of the coordinate along axis a goes to its interleaved position.
-    int bits[3], maxb = 0;
-    for (int a = 0; a < 3; ++a) {
-        bits[a] = ilog2(dim[a]);
-        maxb = std::max(maxb, bits[a]);
-    }
-    int pos[3][16];
-    int p = 0;
-    for (int l = 0; l < maxb; ++l)
-        for (int a = 0; a < 3; ++a)
-            if (l < bits[a])
-                pos[a][l] = p++;
-    hg.parts.assign(dim[0] + dim[1] + dim[2], 0u);
-    int64_t off = 0;
-    for (int a = 0; a < 3; ++a) {
-        for (int64_t c = 0; c < dim[a]; ++c) {
-            uint32_t code = 0;
-            for (int l = 0; l < bits[a]; ++l)
-                code |= (uint32_t)((c >> l) & 1) << pos[a][l];
-            hg.parts[off + c] = code;
-        }
-        off += dim[a];
-    }
+    return std::max<int64_t>(512, next_pow2((int64_t)std::ceil(cpp * (double)n)));
 }
+
+// Largest dim[0] + dim[1] + dim[2] of a grid with power-of-two dims of at most kMaxDim cells each
+// and at most `cap` cells in all (the sum is largest when the dims are as unequal as possible).
+int64_t part_bound(int64_t cap)
+{
+    int64_t left = cap, sum = 0;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t d = std::max<int64_t>(1, std::min<int64_t>(kMaxDim, left));
+        sum += d;
+        left = std::max<int64_t>(1, left / d);
+    }
+    return sum;
+}
+
+// Carves 256-byte aligned pieces out of one allocation: a sizing pass (base == nullptr) adds up
+// the bytes, a second pass hands out the pointers.
+struct Carver {
+    char *base = nullptr;
+    size_t off = 0;
+    template <typename P>
+    void take(P *&dst, size_t bytes)
+    {
+        off = (off + 255) & ~(size_t)255;
+        dst = base ? (P *)(base + off) : nullptr;
+        off += bytes;
+    }
+};
+
+// Page-locked staging for the per-call metadata upload and statistics read-back. One buffer per
+// host thread, grown on demand and kept for the life of the process. Every assembly call
+// synchronises its stream (after the statistics read-back, or before an error return) before it
+// returns, so the next call on the same thread never overwrites a buffer a copy still reads.
+thread_local void *t_stage = nullptr;
+thread_local size_t t_stage_bytes = 0;
+
+void *staging(size_t bytes)
+{
+    if (t_stage_bytes >= bytes)
+        return t_stage;
+    if (t_stage)
+        (void)hipHostFree(t_stage);
+    t_stage = nullptr;
+    t_stage_bytes = 0;
+    const size_t want = std::max<size_t>(bytes, 64 << 10);
+    if (hipHostMalloc(&t_stage, want, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        t_stage = nullptr;
+        return nullptr;
+    }
+    t_stage_bytes = want;
+    return t_stage;
+}
+
+// Occupancy of the persistent assembly kernel (blocks per CU) per (precision, n, K), queried once.
+std::atomic<int> g_occupancy[2][2][kMaxK + 1];
+std::atomic<int> g_n_cu{0};
 
 template <typename T>
 mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<int64_t> &offs,
@@ -290,8 +239,34 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     if (!is_device_pointer(points, device))
         return fail(MVGD_EINVAL, "points is not device memory of the current device");
 
-    ScratchList tmp;
-    tmp.s = stream;
+    // ---- 1. sizes, all known on the host: cell budgets, groups, part tables -------------------
+    // meta: row offsets, then per cloud: first cell entry, cell budget, first group, first part
+    const double cpp = tunable(p.cells_per_point, kDefaultCellsPerPoint);
+    const size_t n_meta = (size_t)5 * n_clouds + 1;
+    std::vector<int64_t> meta(n_meta);
+    int64_t cell_total = 0, group_total = 0, part_total = 0, max_n = 0;
+    for (int c = 0; c < n_clouds; ++c) {
+        const int64_t n = offs[c + 1] - offs[c];
+        const int64_t cap = cell_budget(n, cpp);
+        meta[n_clouds + 1 + c] = cell_total;
+        meta[2 * n_clouds + 1 + c] = cap;
+        meta[3 * n_clouds + 1 + c] = group_total;
+        meta[4 * n_clouds + 1 + c] = part_total;
+        cell_total += cap;
+        group_total += (n + kWave - 1) / kWave;
+        part_total += part_bound(cap);
+        max_n = std::max(max_n, n);
+    }
+    for (int c = 0; c <= n_clouds; ++c)
+        meta[c] = offs[c];
+    if (cell_total >= (int64_t)UINT32_MAX - 1)
+        return fail(MVGD_EUNSUPPORTED, "cell table too large (%lld cells)", (long long)cell_total);
+    std::vector<int64_t> lvl_n; // scan levels over the cell table
+    for (int64_t m = cell_total; m > 1; m = (m + kScanTile - 1) / kScanTile)
+        lvl_n.push_back(m);
+    if (lvl_n.empty())
+        lvl_n.push_back(std::max<int64_t>(cell_total, 1));
+
     mvgd_matrix *L = new (std::nothrow) mvgd_matrix();
     if (!L)
         return fail(MVGD_ENOMEM, "host allocation failed");
@@ -304,25 +279,85 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     L->n_clouds = n_clouds;
     L->ld = (n_total + kWave - 1) / kWave * kWave;
     L->stream = stream;
+    void *scratch = nullptr;
+    bool staged = false; // a copy from/to the staging buffer may be in flight
     struct Guard {
         mvgd_matrix *&L;
-        ~Guard() { if (L) release(L); }
-    } guard{L};
-#define MVGD_ALLOC(dst, nbytes_, what)                                                            \
-    do {                                                                                          \
-        if (tmp.alloc(&(dst), (nbytes_)) != hipSuccess)                                           \
-            return fail(MVGD_ENOMEM, "device allocation failed (%s, %zu bytes)", what,            \
-                        (size_t)(nbytes_));                                                       \
-    } while (0)
-#define MVGD_KEEP(dst, nbytes_, what)                                                             \
-    do {                                                                                          \
-        void *v_ = nullptr;                                                                       \
-        if (dev_alloc(&v_, (nbytes_), stream) != hipSuccess)                                      \
-            return fail(MVGD_ENOMEM, "device allocation failed (%s, %zu bytes)", what,            \
-                        (size_t)(nbytes_));                                                       \
-        dst = (decltype(dst))v_;                                                                  \
-        L->bytes += (nbytes_);                                                                    \
-    } while (0)
+        void *&scratch;
+        bool &staged;
+        hipStream_t s;
+        ~Guard()
+        {
+            if (staged)
+                (void)hipStreamSynchronize(s);
+            if (scratch)
+                (void)hipFreeAsync(scratch, s);
+            if (L)
+                release(L);
+        }
+    } guard{L, scratch, staged, stream};
+
+    // ---- 2. two allocations: the handle's arrays and the assembly scratch ----------------------
+    const size_t vsz = sizeof(T);
+    const bool keep_diag = (p.flags & MVGD_FLAG_KEEP_DIAG) != 0;
+    auto carve_handle = [&](Carver &cv) {
+        cv.take(L->perm, sizeof(int32_t) * n_total);
+        cv.take(L->ell_col, sizeof(int32_t) * (size_t)(K + 1) * L->ld);
+        char *val = nullptr;
+        cv.take(val, vsz * (size_t)(K + 1) * L->ld);
+        L->ell_val = val;
+        cv.take(L->grids, sizeof(CloudGrid) * n_clouds);
+        cv.take(L->counters, sizeof(unsigned long long) * 8);
+        if (keep_diag) {
+            cv.take(L->row_h, sizeof(double) * n_total);
+            cv.take(L->row_flags, (size_t)n_total);
+        }
+    };
+    int64_t *d_meta;
+    CloudStats *d_stats;
+    uint32_t *d_parts, *d_counts, *d_start, *d_keys, *d_slots;
+    unsigned int *d_queue;
+    int32_t *d_iperm;
+    Pt<T> *d_spts;
+    std::vector<uint32_t *> lvl_sum(lvl_n.size()), lvl_off(lvl_n.size());
+    auto carve_scratch = [&](Carver &cv) {
+        cv.take(d_meta, sizeof(int64_t) * n_meta);
+        cv.take(d_stats, sizeof(CloudStats) * n_clouds);
+        cv.take(d_parts, sizeof(uint32_t) * part_total);
+        cv.take(d_counts, sizeof(uint32_t) * cell_total);
+        cv.take(d_start, sizeof(uint32_t) * (cell_total + 1));
+        cv.take(d_keys, sizeof(uint32_t) * n_total);
+        cv.take(d_slots, sizeof(uint32_t) * n_total);
+        cv.take(d_spts, sizeof(Pt<T>) * n_total);
+        cv.take(d_queue, sizeof(unsigned int) * 8);
+        cv.take(d_iperm, sizeof(int32_t) * n_total);
+        for (size_t l = 0; l < lvl_n.size(); ++l) {
+            const int64_t tiles = (lvl_n[l] + kScanTile - 1) / kScanTile;
+            cv.take(lvl_sum[l], sizeof(uint32_t) * tiles);
+            cv.take(lvl_off[l], sizeof(uint32_t) * tiles);
+        }
+    };
+    {
+        Carver h, t;
+        carve_handle(h);
+        carve_scratch(t);
+        if (dev_alloc(&L->block, h.off, stream) != hipSuccess)
+            return fail(MVGD_ENOMEM, "device allocation failed (matrix, %zu bytes)", h.off);
+        L->bytes = h.off;
+        if (dev_alloc(&scratch, t.off, stream) != hipSuccess)
+            return fail(MVGD_ENOMEM, "device allocation failed (assembly scratch, %zu bytes)",
+                        t.off);
+        h = Carver{(char *)L->block, 0};
+        t = Carver{(char *)scratch, 0};
+        carve_handle(h);
+        carve_scratch(t);
+    }
+    const size_t meta_bytes = sizeof(int64_t) * n_meta;
+    const size_t stats_off = (meta_bytes + 255) & ~(size_t)255;
+    char *stage = (char *)staging(stats_off + sizeof(CloudStats) * n_clouds);
+    if (!stage)
+        return fail(MVGD_ENOMEM, "page-locked staging allocation failed");
+    memcpy(stage, meta.data(), meta_bytes);
 
     if (p.flags & MVGD_FLAG_TIME) {
         for (hipEvent_t &e : L->ev)
@@ -330,120 +365,37 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
                 return fail(MVGD_EDEVICE, "hipEventCreate failed");
         (void)hipEventRecord(L->ev[0], stream);
     }
-    // ---- 1. per-cloud bounding box and finiteness (the one synchronisation) -------------------
-    const Proj proj = binning_projection(n_amb);
-    int64_t *d_offs = nullptr;
-    CloudStats *d_stats = nullptr;
-    MVGD_ALLOC(d_offs, sizeof(int64_t) * offs.size(), "offsets");
-    MVGD_ALLOC(d_stats, sizeof(CloudStats) * n_clouds, "stats");
-    if (hipMemcpyAsync(d_offs, offs.data(), sizeof(int64_t) * offs.size(), hipMemcpyHostToDevice,
-                       stream) != hipSuccess)
+    // ---- 3. bounding boxes, grid plan, binning (no host round trip) ----------------------------
+    staged = true;
+    if (hipMemcpyAsync(d_meta, stage, meta_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
         return fail(MVGD_EDEVICE, "copy of cloud offsets failed");
-    stats_init_kernel<<<(n_clouds + 255) / 256, 256, 0, stream>>>(d_stats, n_clouds);
+    stats_init_kernel<<<(std::max(n_clouds, 8) + 255) / 256, 256, 0, stream>>>(
+        d_stats, n_clouds, L->counters, d_queue);
+    const Proj proj = binning_projection(n_amb);
     {
-        int64_t max_n = 0;
-        for (int c = 0; c < n_clouds; ++c)
-            max_n = std::max(max_n, offs[c + 1] - offs[c]);
         const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(512, (max_n + 2047) / 2048));
         if (n_amb == 3)
-            bbox_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_offs, proj, d_stats);
+            bbox_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
         else
-            bbox_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_offs, proj, d_stats);
+            bbox_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
     }
-    if (mvgd_status st = check_launch("bbox"); st != MVGD_OK)
-        return st;
-    std::vector<CloudStats> hs(n_clouds);
-    if (hipMemcpyAsync(hs.data(), d_stats, sizeof(CloudStats) * n_clouds, hipMemcpyDeviceToHost,
-                       stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
-        return fail(MVGD_EDEVICE, "reading the bounding boxes failed: %s",
-                    hipGetErrorString(hipGetLastError()));
-    auto decode = [](unsigned long long u) {
-        unsigned long long b = (u >> 63) ? (u & 0x7fffffffffffffffull) : ~u;
-        double d;
-        memcpy(&d, &b, sizeof d);
-        return d;
-    };
-    // ---- 2. grids -------------------------------------------------------------------------------
-    std::vector<HostGrid> hg(n_clouds);
-    std::vector<uint32_t> parts;
-    int64_t cell_total = 0, group_total = 0;
-    for (int c = 0; c < n_clouds; ++c) {
-        if (hs[c].nonfinite)
-            return fail(MVGD_EINVAL, "cloud %d has %llu non-finite coordinates", c,
-                        (unsigned long long)hs[c].nonfinite);
-        double mn[4], mx[4], pmn[3], pmx[3];
-        for (int a = 0; a < n_amb; ++a) {
-            mn[a] = decode(hs[c].mn[a]);
-            mx[a] = decode(hs[c].mx[a]);
-        }
-        for (int a = 0; a < 3; ++a) {
-            pmn[a] = decode(hs[c].pmn[a]);
-            pmx[a] = decode(hs[c].pmx[a]);
-        }
-        const int64_t n = offs[c + 1] - offs[c];
-        plan_grid(mn, mx, pmn, pmx, proj, n_amb, n, K, offs[c], p, hg[c]);
-        CloudGrid &g = hg[c].g;
-        g.cell0 = cell_total;
-        g.group0 = group_total;
-        g.part0 = (int64_t)parts.size();
-        parts.insert(parts.end(), hg[c].parts.begin(), hg[c].parts.end());
-        cell_total += (int64_t)g.dim[0] * g.dim[1] * g.dim[2];
-        group_total += (n + kWave - 1) / kWave;
+    {
+        PlanArgs pa;
+        memset(&pa, 0, sizeof pa);
+        pa.stats = d_stats;
+        pa.meta = d_meta;
+        pa.n_clouds = n_clouds;
+        pa.n_amb = n_amb;
+        pa.K = K;
+        pa.alpha = tunable(p.cell_alpha, kDefaultCellAlpha);
+        pa.mu = tunable(p.radius_mu, kDefaultRadiusMu);
+        pa.proj = proj;
+        pa.grids = L->grids;
+        pa.parts = d_parts;
+        plan_kernel<<<n_clouds, 256, 0, stream>>>(pa);
     }
-    if (cell_total >= (int64_t)UINT32_MAX - 1)
-        return fail(MVGD_EUNSUPPORTED, "cell table too large (%lld cells)", (long long)cell_total);
-    std::vector<CloudGrid> grids(n_clouds);
-    for (int c = 0; c < n_clouds; ++c)
-        grids[c] = hg[c].g;
-
-    // ---- 3. allocations ---------------------------------------------------------------------------
-    uint32_t *d_parts, *d_counts, *d_start, *d_keys, *d_slots;
-    Pt<T> *d_spts;
-    MVGD_ALLOC(d_parts, sizeof(uint32_t) * parts.size(), "morton tables");
-    MVGD_ALLOC(d_counts, sizeof(uint32_t) * cell_total, "cell counts");
-    MVGD_ALLOC(d_start, sizeof(uint32_t) * (cell_total + 1), "cell starts");
-    MVGD_ALLOC(d_keys, sizeof(uint32_t) * n_total, "keys");
-    MVGD_ALLOC(d_slots, sizeof(uint32_t) * n_total, "slots");
-    MVGD_ALLOC(d_spts, sizeof(Pt<T>) * n_total, "sorted points");
-    unsigned int *d_queue;
-    MVGD_ALLOC(d_queue, sizeof(unsigned int) * 8, "work queues");
-    int32_t *d_iperm;
-    MVGD_ALLOC(d_iperm, sizeof(int32_t) * n_total, "inverse permutation");
-    // scan levels
-    std::vector<int64_t> lvl_n;
-    for (int64_t m = cell_total; m > 1; m = (m + kScanTile - 1) / kScanTile)
-        lvl_n.push_back(m);
-    if (lvl_n.empty())
-        lvl_n.push_back(std::max<int64_t>(cell_total, 1));
-    std::vector<uint32_t *> lvl_sum(lvl_n.size()), lvl_off(lvl_n.size());
-    for (size_t l = 0; l < lvl_n.size(); ++l) {
-        const int64_t tiles = (lvl_n[l] + kScanTile - 1) / kScanTile;
-        MVGD_ALLOC(lvl_sum[l], sizeof(uint32_t) * tiles, "scan sums");
-        MVGD_ALLOC(lvl_off[l], sizeof(uint32_t) * tiles, "scan offsets");
-    }
-    const size_t vsz = sizeof(T);
-    MVGD_KEEP(L->perm, sizeof(int32_t) * n_total, "permutation");
-    MVGD_KEEP(L->ell_col, sizeof(int32_t) * (size_t)(K + 1) * L->ld, "columns");
-    MVGD_KEEP(L->ell_val, vsz * (size_t)(K + 1) * L->ld, "values");
-    MVGD_KEEP(L->grids, sizeof(CloudGrid) * n_clouds, "grids");
-    MVGD_KEEP(L->counters, sizeof(unsigned long long) * 8, "counters");
-    if (p.flags & MVGD_FLAG_KEEP_DIAG) {
-        MVGD_KEEP(L->row_h, sizeof(double) * n_total, "row h");
-        MVGD_KEEP(L->row_flags, n_total, "row flags");
-    }
-
-    // ---- 4. binning: keys, counting sort -------------------------------------------------------
-    if (hipMemcpyAsync(d_parts, parts.data(), sizeof(uint32_t) * parts.size(),
-                       hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(L->grids, grids.data(), sizeof(CloudGrid) * n_clouds,
-                       hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemsetAsync(d_counts, 0, sizeof(uint32_t) * cell_total, stream) != hipSuccess ||
-        hipMemsetAsync(L->counters, 0, sizeof(unsigned long long) * 8, stream) != hipSuccess)
-        return fail(MVGD_EDEVICE, "grid upload failed");
-    int64_t max_n = 0;
-    for (int c = 0; c < n_clouds; ++c)
-        max_n = std::max(max_n, offs[c + 1] - offs[c]);
+    if (hipMemsetAsync(d_counts, 0, sizeof(uint32_t) * cell_total, stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "clearing the cell counts failed");
     const int bx = (int)std::min<int64_t>(2048, (max_n + 255) / 256);
     if (n_amb == 3)
         key_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
@@ -462,8 +414,6 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
             o = lvl_off[l];
         }
         for (size_t l = lvl_n.size(); l-- > 1;) {
-            const int64_t tiles = (lvl_n[l - 1] + kScanTile - 1) / kScanTile;
-            (void)tiles;
             uint32_t *dst = (l - 1 == 0) ? d_start : lvl_off[l - 2];
             scan_add_kernel<<<(unsigned)((lvl_n[l - 1] + kScanTile - 1) / kScanTile), kScanThreads,
                               0, stream>>>(dst, lvl_off[l - 1], lvl_n[l - 1]);
@@ -475,6 +425,19 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
                                                                d_iperm);
     if (mvgd_status st = check_launch("binning"); st != MVGD_OK)
         return st;
+
+    // ---- 4. the one synchronisation: non-finite coordinates are rejected before the search ----
+    CloudStats *hs = (CloudStats *)(stage + stats_off);
+    if (hipMemcpyAsync(hs, d_stats, sizeof(CloudStats) * n_clouds, hipMemcpyDeviceToHost,
+                       stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return fail(MVGD_EDEVICE, "reading the cloud statistics failed: %s",
+                    hipGetErrorString(hipGetLastError()));
+    staged = false;
+    for (int c = 0; c < n_clouds; ++c)
+        if (hs[c].nonfinite)
+            return fail(MVGD_EINVAL, "cloud %d has %llu non-finite coordinates", c,
+                        (unsigned long long)hs[c].nonfinite);
 
     // ---- 5. fused neighbour search + fit + stencil ------------------------------------------
     AsmParams ap;
@@ -503,15 +466,20 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
     unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
     if (persistent) {
-        int per_cu = 0, n_cu = 0;
-        auto kern = n_amb == 3 ? assemble_persistent_kernel<T, 3> : assemble_persistent_kernel<T, 4>;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess ||
-            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
-            return fail(MVGD_EDEVICE, "occupancy query failed");
-        const int64_t resident = (int64_t)std::max(per_cu, 1) * std::max(n_cu, 1);
+        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb == 4][K];
+        int per_cu = occ.load(), n_cu = g_n_cu.load();
+        if (per_cu <= 0 || n_cu <= 0) {
+            auto kern = n_amb == 3 ? assemble_persistent_kernel<T, 3> : assemble_persistent_kernel<T, 4>;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess ||
+                hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+                return fail(MVGD_EDEVICE, "occupancy query failed");
+            per_cu = std::max(per_cu, 1);
+            n_cu = std::max(n_cu, 1);
+            occ.store(per_cu);
+            g_n_cu.store(n_cu);
+        }
+        const int64_t resident = (int64_t)per_cu * n_cu;
         nblk = (unsigned)std::min<int64_t>((resident + 7) / 8 * 8, ap.groups_per_xcd * 8);
-        if (hipMemsetAsync(d_queue, 0, sizeof(unsigned int) * 8, stream) != hipSuccess)
-            return fail(MVGD_EDEVICE, "queue reset failed");
     }
     if (L->ev[1])
         (void)hipEventRecord(L->ev[1], stream);
@@ -530,10 +498,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         return st;
     if (L->ev[2])
         (void)hipEventRecord(L->ev[2], stream);
-#undef MVGD_ALLOC
-#undef MVGD_KEEP
     *out = L;
-    L = nullptr; // ownership passes to the caller; scratch is freed stream-ordered
+    L = nullptr; // ownership passes to the caller; the scratch is freed stream-ordered
     return MVGD_OK;
 }
 
@@ -743,8 +709,8 @@ mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t)
         return fail(MVGD_EINVAL, "NULL argument");
     if (!L->ev[0])
         return fail(MVGD_EINVAL, "the matrix was assembled without MVGD_FLAG_TIME");
-    if (hipStreamSynchronize(L->stream) != hipSuccess)
-        return fail(MVGD_EDEVICE, "stream synchronisation failed");
+    if (hipEventSynchronize(L->have_apply ? L->ev[4] : L->ev[2]) != hipSuccess)
+        return fail(MVGD_EDEVICE, "event synchronisation failed");
     memset(t, 0, sizeof *t);
     if (hipEventElapsedTime(&t->bin_ms, L->ev[0], L->ev[1]) != hipSuccess ||
         hipEventElapsedTime(&t->assemble_ms, L->ev[1], L->ev[2]) != hipSuccess)
