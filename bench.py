@@ -121,12 +121,21 @@ def bench_serving(args):
     print(f"[bench] serving: {len(reqs)} requests over {args.serve_seconds} s at "
           f"{args.serve_rate}/s, {sum(r.points.shape[0] for r in reqs)} points",
           file=sys.stderr, flush=True)
+    # warm-up: buffers sized for the largest request (and a few-request batch), the library's
+    # kernels loaded, the device allocators' pools grown
+    n_max = max(r.points.shape[0] for r in reqs)
     warm = serve.make_requests(duration_s=0.05, rate_hz=200, seed=99, max_requests=4)
-    serve.Server(precision="fp32").run(warm)
-    serve.one_at_a_time(warm)
-    mixed = serve.Server(precision="fp32", n_streams=4, max_batch=16).run(reqs).summary()
+    big = max(reqs, key=lambda r: r.points.shape[0])
+    warm[-1] = serve.Request(-1, warm[-1].arrival, big.points, big.rhs, big.k)
+    srv = serve.Server(precision="fp32", n_streams=4, max_batch=16)
+    srv.reserve(4 * n_max)
+    srv.run(warm)
+    base_srv = serve.Server(precision="fp64", n_streams=1, max_batch=1)
+    base_srv.reserve(n_max)
+    base_srv.run(warm, batching=False)
+    mixed = srv.run(reqs).summary()
     print(f"[bench] batched fp32: {mixed}", file=sys.stderr, flush=True)
-    base = serve.one_at_a_time(reqs, precision="fp64").summary()
+    base = base_srv.run(reqs, batching=False).summary()
     print(f"[bench] one-at-a-time fp64: {base}", file=sys.stderr, flush=True)
     out = {"metric": "serving p99 latency (assemble + 8 applies per request)",
            "value": mixed["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": mixed["requests"],

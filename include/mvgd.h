@@ -182,6 +182,14 @@ mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t);
 /* mvgd_info -- sizes and counters; waits for the handle's stream (synchronous). */
 mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info);
 
+/* mvgd_pool_trim -- device memory of the current device that the library keeps cached. Handles
+ * and assembly scratch come from a stream-ordered pool owned by the library, one per device; freed
+ * memory stays in the pool for later calls (no fresh mapping per assembly). This call returns the
+ * unused part of the current device's pool to the system, keeping at most keep_bytes (0: all of
+ * it). Memory of live handles is never released. MVGD_EDEVICE if the pool cannot be created or
+ * trimmed. */
+mvgd_status mvgd_pool_trim(size_t keep_bytes);
+
 /* Human-readable name of a status code (static string). */
 const char *mvgd_status_str(mvgd_status s);
 

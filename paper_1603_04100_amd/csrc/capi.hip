@@ -53,6 +53,44 @@ std::mutex g_fail_mu;
 std::string g_fail_seen;
 long g_fail_base = 0;
 
+// The library's own stream-ordered memory pool per device. Its release threshold is unbounded:
+// memory freed by mvgd_free and by the end of an assembly stays mapped in the pool for the next
+// call (a pool that trims at every synchronisation maps fresh pages on every assembly);
+// mvgd_pool_trim hands it back.
+constexpr int kMaxDevices = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[kMaxDevices] = {};
+
+hipError_t device_pool(hipMemPool_t *out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool[dev]) {
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof props);
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if ((e = hipMemPoolCreate(&pool, &props)) != hipSuccess)
+            return e;
+        uint64_t keep = UINT64_MAX;
+        if ((e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep)) != hipSuccess) {
+            (void)hipMemPoolDestroy(pool);
+            return e;
+        }
+        g_pool[dev] = pool;
+    }
+    *out = g_pool[dev];
+    return hipSuccess;
+}
+
 hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s)
 {
     *p = nullptr;
@@ -69,7 +107,11 @@ hipError_t dev_alloc(void **p, size_t bytes, hipStream_t s)
     }
     if (bytes == 0)
         bytes = 16;
-    return hipMallocAsync(p, bytes, s);
+    hipMemPool_t pool = nullptr;
+    hipError_t e = device_pool(&pool);
+    if (e != hipSuccess)
+        return e;
+    return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
 
 int64_t next_pow2(int64_t v)
@@ -719,6 +761,16 @@ mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t)
         if (hipEventElapsedTime(&t->apply_ms, L->ev[3], L->ev[4]) != hipSuccess)
             return fail(MVGD_EDEVICE, "event timing failed");
         t->have_apply = 1;
+    }
+    return MVGD_OK;
+}
+
+mvgd_status mvgd_pool_trim(size_t keep_bytes)
+{
+    hipMemPool_t pool = nullptr;
+    if (device_pool(&pool) != hipSuccess || hipMemPoolTrimTo(pool, keep_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MVGD_EDEVICE, "trimming the device memory pool failed");
     }
     return MVGD_OK;
 }

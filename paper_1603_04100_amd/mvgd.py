@@ -24,7 +24,7 @@ MVGD_FP64, MVGD_FP32_MIXED = 0, 1
 MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 4, 8
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
-           "mvgd_timing", "mvgd_status_str", "mvgd_last_error", "mvgd_version")
+           "mvgd_timing", "mvgd_pool_trim", "mvgd_status_str", "mvgd_last_error", "mvgd_version")
 
 
 class MvgdError(RuntimeError):
@@ -79,6 +79,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mvgd_timing.restype = i32
     lib.mvgd_info.argtypes = [vp, ctypes.POINTER(mvgd_info_t)]
     lib.mvgd_info.restype = i32
+    lib.mvgd_pool_trim.argtypes = [ctypes.c_size_t]
+    lib.mvgd_pool_trim.restype = i32
     lib.mvgd_status_str.argtypes = [i32]
     lib.mvgd_status_str.restype = ctypes.c_char_p
     lib.mvgd_last_error.argtypes = []
@@ -216,6 +218,11 @@ def mvgd_timing(L: Matrix) -> dict:
     t = mvgd_timing_t()
     _check(_lib.mvgd_timing(L.handle, ctypes.byref(t)))
     return {name: getattr(t, name) for name, _ in mvgd_timing_t._fields_}
+
+
+def mvgd_pool_trim(keep_bytes: int = 0):
+    """Return the unused device memory of the library's pool (current device) to the system."""
+    _check(_lib.mvgd_pool_trim(int(keep_bytes)))
 
 
 def version() -> int:

@@ -329,6 +329,22 @@ def test_allocation_failure_cleans_up(mv):
     ref.free()
 
 
+def test_pool_trim_keeps_live_handles(mv):
+    pts = torch.tensor(clouds.sphere(3000, 1, 20).points, device=DEV)
+    A = mv.mvgd_assemble(pts, 20)
+    rp, col, val = mv.mvgd_csr(A)
+    B = mv.mvgd_assemble(pts, 20)
+    B.free()
+    mv.mvgd_pool_trim(0)
+    r2, c2, v2 = mv.mvgd_csr(A)
+    assert torch.equal(c2, col) and torch.equal(v2, val)
+    C = mv.mvgd_assemble(pts, 20)
+    r3, c3, v3 = mv.mvgd_csr(C)
+    assert torch.equal(c3, col) and torch.equal(v3, val)
+    A.free()
+    C.free()
+
+
 # ----------------------------------------------------------------------------------------------
 # launch modes and tuning change only performance: results are bit-identical
 # ----------------------------------------------------------------------------------------------
