@@ -60,7 +60,7 @@ def _load():
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
     lib.oracle_knn.argtypes = [P, i64, i32, i32, P, i64, P, P, i32]
     lib.oracle_knn.restype = i32
-    lib.oracle_rows.argtypes = [P, i64, i32, i32, i32, i32, i32, f64, P, i64, P, P, P, i32]
+    lib.oracle_rows.argtypes = [P, i64, i32, i32, i32, i32, i32, f64, f64, P, i64, P, P, P, i32]
     lib.oracle_rows.restype = i32
     lib.oracle_apply.argtypes = [i64, P, P, P, i32, P, P]
     lib.oracle_apply.restype = i32
@@ -108,9 +108,11 @@ def knn(points, k: int, rows=None, nthreads: int = 0):
 
 
 def rows(points, k: int, rows=None, d: int = 2, variant: str = "mvgd", h_override=None,
-         diag: bool = False, nthreads: int = 0):
+         diag: bool = False, nthreads: int = 0, weight_nbr: float = 1.0):
     """MVGD rows (or the plain LS variant) for the given rows.
 
+    weight_nbr: least-squares weight of every neighbour (p_i has weight 1); 1 is the unweighted
+    fit, 1/k the moving-least-squares weights of the paper's comparison (Sec. 4).
     Returns (cols [R, K+1] int64 ascending, vals [R, K+1] float64[, diag [R, 64]]).
     """
     p = _points(points)
@@ -121,8 +123,8 @@ def rows(points, k: int, rows=None, d: int = 2, variant: str = "mvgd", h_overrid
     var = {"mvgd": 0, "ls": 1}[variant]
     use_h = 0 if h_override is None else 1
     rc = _load().oracle_rows(_ptr(p), p.shape[0], p.shape[1], d, k, var, use_h,
-                             float(h_override or 0.0), _ptr(r), nr, _ptr(cols), _ptr(vals),
-                             _ptr(dg), nthreads)
+                             float(h_override or 0.0), float(weight_nbr), _ptr(r), nr,
+                             _ptr(cols), _ptr(vals), _ptr(dg), nthreads)
     if rc == -2:
         raise ValueError("oracle_rows: non-finite coordinates")
     if rc != 0:
@@ -131,10 +133,10 @@ def rows(points, k: int, rows=None, d: int = 2, variant: str = "mvgd", h_overrid
 
 
 def assemble(points, k: int, d: int = 2, variant: str = "mvgd", h_override=None,
-             nthreads: int = 0):
+             nthreads: int = 0, weight_nbr: float = 1.0):
     """The whole matrix as CSR: (row_ptr int64 [N+1], cols int64 [nnz], vals float64 [nnz])."""
     cols, vals = rows(points, k, None, d=d, variant=variant, h_override=h_override,
-                      nthreads=nthreads)
+                      nthreads=nthreads, weight_nbr=weight_nbr)
     n = cols.shape[0]
     row_ptr = np.arange(n + 1, dtype=np.int64) * (k + 1)
     return row_ptr, cols.reshape(-1), vals.reshape(-1)
@@ -166,3 +168,44 @@ def lb_coefficients(a, d: int = 2):
     if rc != 0:
         raise ValueError("degenerate metric")
     return G.reshape(d, d), q
+
+
+def row_stats(row_ids, cols, vals):
+    """Sign statistics of matrix rows (the property Sec. 3.2 argues for: the centre modification
+    pushes the off-diagonal entries to the sign opposite to the negative diagonal, towards
+    an M-matrix -L, where plain least-squares rows have off-diagonal entries of mixed sign).
+
+    row_ids [R]: the row index of each row; cols/vals [R, K+1]: the row's columns (ascending,
+    containing row_ids[r] once) and values. Per row, with d the diagonal value and o_j the
+    off-diagonal values in column order:
+      neg_mass = sum_j max(0, -o_j), one float64 addition per entry in column order;
+      ratio    = neg_mass / |d| (NaN where d == 0; rows that sum to zero are diagonally
+                 dominant exactly when ratio == 0);
+      m_row    = d < 0 and every o_j >= 0.
+    Returns (per-row dict of arrays, totals dict).
+    """
+    row_ids = np.asarray(row_ids, dtype=np.int64)
+    cols = np.asarray(cols)
+    vals = np.asarray(vals, dtype=np.float64)
+    R = vals.shape[0]
+    ratio = np.empty(R)
+    m_row = np.zeros(R, dtype=bool)
+    diag_neg = np.zeros(R, dtype=bool)
+    n_off_neg = 0
+    for r in range(R):
+        on = cols[r] == row_ids[r]
+        d = float(vals[r][on][0])
+        off = vals[r][~on]
+        neg = 0.0
+        for v in off:
+            neg += max(0.0, -float(v))
+        ratio[r] = neg / abs(d) if d != 0.0 else np.nan
+        diag_neg[r] = d < 0.0
+        m_row[r] = d < 0.0 and bool((off >= 0.0).all())
+        n_off_neg += int((off < 0.0).sum())
+    ok = ~np.isnan(ratio)
+    totals = {"n_rows": R, "n_diag_negative": int(diag_neg.sum()), "n_m_rows": int(m_row.sum()),
+              "n_offdiag_negative": n_off_neg,
+              "max_ratio": float(ratio[ok].max()) if ok.any() else 0.0,
+              "mean_ratio": float(ratio[ok].mean()) if ok.any() else 0.0}
+    return {"ratio": ratio, "m_row": m_row, "diag_negative": diag_neg}, totals

@@ -33,6 +33,10 @@
  *       ell = (tau, -q1, -q2, 2 G11, 2 G12, 2 G22) on b = (b00, b10, b01, b20, b11, b02).
  *       The plain least-squares variant (Sec. 2) uses ell with tau = 0 and no centre term.
  *   O10 weights w = V (V^T V)^-1 D ell, D = diag of the h scaling, then w_centre -= tau.
+ *       Weighted least squares (the moving-least-squares comparison of Sec. 4, weight 1 at p_i
+ *       and w at every neighbour; w = 1/K there): both fits minimise sum_r w_r (residual_r)^2,
+ *       i.e. V and the data are scaled row-wise by sqrt(w_r) before the QR, and the row becomes
+ *       W V (V^T W V)^-1 D ell. w = 1 is the unweighted fit.
  *   O11 the row: columns {i} u N(i) ascending, explicit zeros kept.
  *   O12 apply: y_i = sum_j L_ij x_j in column order.
  *
@@ -307,6 +311,7 @@ int oracle_lb_coefficients(int d, int n_codim, const double *a, double *G, doubl
 typedef struct {
     int n, d, K, variant, use_h;
     double h_override;
+    double w_nbr; /* least-squares weight of every neighbour (p_i has weight 1) */
 } oparams;
 
 /* scratch per thread */
@@ -394,6 +399,7 @@ static void mvgd_row(const double *P, int64_t N, const oparams *pr, int64_t i, o
     double a_unscaled[3 * 6] = {0}, G[4] = {0}, q[2] = {0}, ell[6] = {0}, tau = 0.0;
     qr_t f = {K + 1, m, s->V, {0}, {0}};
     double rmax = 0.0, rmin = INFINITY;
+    const double sw = sqrt(pr->w_nbr); /* row scale of the neighbours in the weighted fits */
     if (!degenerate) {
         /* O6 */
         const double ih = 1.0 / h;
@@ -411,6 +417,9 @@ static void mvgd_row(const double *P, int64_t N, const oparams *pr, int64_t i, o
             } else {
                 row[0] = 1.0; row[1] = xi; row[2] = xi * xi;
             }
+            if (r > 0 && pr->w_nbr != 1.0)
+                for (int t = 0; t < m; ++t)
+                    row[t] *= sw;
         }
         qr_factor(&f);
         for (int k = 0; k < m; ++k) {
@@ -432,7 +441,7 @@ static void mvgd_row(const double *P, int64_t N, const oparams *pr, int64_t i, o
         for (int c = 0; c < nc; ++c) {
             s->y[0] = 0.0;
             for (int k = 0; k < K; ++k)
-                s->y[k + 1] = z[k * 3 + c];
+                s->y[k + 1] = (pr->w_nbr != 1.0) ? z[k * 3 + c] * sw : z[k * 3 + c];
             qr_apply_qt(&f, s->y);
             qr_solve_r(&f, s->y);
             for (int t = 0; t < m; ++t)
@@ -461,6 +470,9 @@ static void mvgd_row(const double *P, int64_t N, const oparams *pr, int64_t i, o
         for (int r = m; r <= K; ++r)
             s->w[r] = 0.0;
         qr_apply_q(&f, s->w);
+        if (pr->w_nbr != 1.0) /* W V y = W^1/2 (W^1/2 V) y */
+            for (int r = 1; r <= K; ++r)
+                s->w[r] *= sw;
         s->w[0] -= tau;
     }
     /* O11: merge the centre into the ascending neighbour list */
@@ -552,19 +564,20 @@ int oracle_knn(const double *P, int64_t N, int n, int K, const int64_t *rows, in
     return 0;
 }
 
-/* MVGD (variant 0) or plain LS (variant 1) rows for the listed rows (rows == NULL: all).
+/* MVGD (variant 0) or plain LS (variant 1) rows for the listed rows (rows == NULL: all), with
+ * least-squares weight w_nbr (> 0) on every neighbour and 1 on p_i (w_nbr = 1: unweighted).
  * out_cols / out_vals: nrows x (K+1), columns ascending. out_diag: nrows x 64 or NULL.
  * Returns 0, -1 on bad arguments, -2 on non-finite coordinates. */
 int oracle_rows(const double *P, int64_t N, int n, int d, int K, int variant, int use_h,
-                double h_override, const int64_t *rows, int64_t nrows, int64_t *out_cols,
-                double *out_vals, double *out_diag, int nthreads)
+                double h_override, double w_nbr, const int64_t *rows, int64_t nrows,
+                int64_t *out_cols, double *out_vals, double *out_diag, int nthreads)
 {
     int rc = check_common(P, N, n, d, K);
     if (rc)
         return rc;
-    if (variant != 0 && variant != 1)
+    if ((variant != 0 && variant != 1) || !(w_nbr > 0.0) || !isfinite(w_nbr))
         return -1;
-    oparams pr = {n, d, K, variant, use_h, h_override};
+    oparams pr = {n, d, K, variant, use_h, h_override, w_nbr};
     int64_t R = rows ? nrows : N;
     const int m = (d == 2) ? 6 : 3;
 #ifdef _OPENMP

@@ -385,7 +385,9 @@ def test_argument_errors(oracle_mod):
 # evaluate the fitted quadratic at the virtual grid nodes (+-h), put U_i at the centre node,
 # and combine the differences with the coefficients of Eq. eqn3 (pinned above).
 # ----------------------------------------------------------------------------------------
-def _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod):
+def _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod, variant="mvgd", w_nbr=1.0):
+    """Weighted variants: LAPACK least squares on rows scaled by sqrt(weight) (weight 1 at p_i,
+    w_nbr at the neighbours). The LS variant puts the fitted value, not U_i, at the centre."""
     n = P.shape[1]
     D = P[nb] - P[i]
     u = D @ frame[:d].T
@@ -396,11 +398,12 @@ def _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod):
     else:
         mono = lambda x: np.stack([np.ones_like(x), x, x * x], -1)
         V = np.vstack([mono(np.zeros(1)), mono(u[:, 0])])
+    sw = np.sqrt(np.concatenate([[1.0], np.full(len(nb), w_nbr)]))
     Z = np.vstack([np.zeros((1, n - d)), z])
-    a = np.linalg.lstsq(V, Z, rcond=None)[0].T
+    a = np.linalg.lstsq(V * sw[:, None], Z * sw[:, None], rcond=None)[0].T
     G, q = oracle_mod.lb_coefficients(a, d)
-    Ui = U[0]
-    b = np.linalg.lstsq(V, U, rcond=None)[0]
+    b = np.linalg.lstsq(V * sw[:, None], U * sw, rcond=None)[0]
+    Ui = U[0] if variant == "mvgd" else b[0]
     if d == 2:
         Uh = lambda x, y: (mono(np.array([x]), np.array([y])) @ b)[0]
         Dx = (Uh(h, 0) - Uh(-h, 0)) / (2 * h)
@@ -415,8 +418,12 @@ def _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod):
     return G[0, 0] * Dxx - q[0] * Dx
 
 
-@pytest.mark.parametrize("which", ["sphere", "torus", "flat4", "circle", "helix"])
-def test_rows_equal_virtual_grid_definition(oracle_mod, which):
+@pytest.mark.parametrize("which,variant,weighted", [
+    ("sphere", "mvgd", False), ("torus", "mvgd", False), ("flat4", "mvgd", False),
+    ("circle", "mvgd", False), ("helix", "mvgd", False),
+    ("sphere", "ls", False), ("flat4", "ls", True), ("torus", "mvgd", True),
+    ("helix", "ls", True), ("circle", "mvgd", True)])
+def test_rows_equal_virtual_grid_definition(oracle_mod, which, variant, weighted):
     rng = np.random.default_rng(7)
     if which == "sphere":
         P, K, d = clouds.sphere(2000, 51, 20).points, 20, 2
@@ -431,7 +438,9 @@ def test_rows_equal_virtual_grid_definition(oracle_mod, which):
         t = rng.uniform(0, 4 * np.pi, 800)
         P, K, d = np.stack([np.cos(t), np.sin(t), 0.3 * t], 1), 8, 1
     rows = np.arange(0, P.shape[0], 41)
-    cols, vals, dg = oracle_mod.rows(P, K, rows=rows, d=d, diag=True)
+    w_nbr = 1.0 / K if weighted else 1.0
+    cols, vals, dg = oracle_mod.rows(P, K, rows=rows, d=d, diag=True, variant=variant,
+                                     weight_nbr=w_nbr)
     n = P.shape[1]
     for r, i in enumerate(rows):
         nb = cols[r][cols[r] != i]
@@ -439,7 +448,7 @@ def test_rows_equal_virtual_grid_definition(oracle_mod, which):
         h = dg[r, 0]
         for _ in range(3):
             U = rng.standard_normal(K + 1)  # U[0] at p_i, then N(i) ascending
-            ref = _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod)
+            ref = _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod, variant, w_nbr)
             Ucol = dict(zip(np.concatenate([[i], nb]), U))
             ours = sum(v * Ucol[c] for c, v in zip(cols[r], vals[r]))
             assert ours == pytest.approx(ref, rel=1e-9, abs=1e-11 * np.abs(vals[r]).sum())
@@ -455,3 +464,82 @@ def test_circle_converges(oracle_mod):
         e = oracle_mod.apply(rp, c, v, np.sin(2 * t)) + 4 * np.sin(2 * t)
         errs.append(np.sqrt((e ** 2).mean()))
     assert errs[0] / errs[2] > 4.0, errs
+
+
+# ----------------------------------------------------------------------------------------
+# Weighted (moving) least squares (Sec. 4: weight 1 at p_i and 1/K at the neighbours)
+# ----------------------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", ["mvgd", "ls"])
+def test_weighted_fits_keep_plane_exactness(oracle_mod, variant):
+    """A weighted fit still reproduces quadratics, so on a plane L f = Delta f exactly and
+    rows sum to zero."""
+    p, basis, _ = clouds.random_plane(500, 3, 4)
+    rng = np.random.default_rng(40)
+    A = rng.standard_normal((3, 3))
+    A = A + A.T
+    f = np.einsum("ni,ij,nj->n", p, A, p) + p @ rng.standard_normal(3)
+    lap = 2.0 * np.trace(basis @ A @ basis.T)
+    rp, cols, vals = oracle_mod.assemble(p, 16, variant=variant, weight_nbr=1.0 / 16)
+    y = oracle_mod.apply(rp, cols, vals, f)
+    v = vals.reshape(-1, 17)
+    assert np.all(np.abs(y - lap) <= 1e-11 * np.abs(v).sum(1) * np.abs(f).max() + 1e-9)
+    assert np.all(np.abs(v.sum(1)) <= 1e-12 * np.abs(v).sum(1))
+
+
+def test_weights_change_the_rows_off_planes(oracle_mod):
+    """On a curved surface the weighted rows differ from the unweighted ones (the weight reaches
+    both fits), and the centre weight 1 dominates as w_nbr -> 0."""
+    cl = clouds.sphere(1500, 31, 20)
+    rows = np.arange(0, 1500, 50)
+    _, v1 = oracle_mod.rows(cl.points, 20, rows=rows)
+    _, vw = oracle_mod.rows(cl.points, 20, rows=rows, weight_nbr=1.0 / 20)
+    assert np.abs(vw - v1).max() > 1e-3 * np.abs(v1).max()
+    with pytest.raises(ValueError):
+        oracle_mod.rows(cl.points, 20, rows=rows, weight_nbr=0.0)
+
+
+# ----------------------------------------------------------------------------------------
+# Row sign statistics (Sec. 3.2: the M-matrix property of the modified difference)
+# ----------------------------------------------------------------------------------------
+def test_row_stats_on_the_printed_rows(oracle_mod):
+    """The paper's two 1-D rows: MVGD (4, 19, -46, 19, 4) is an M-row, LS (2, -1, -2, -1, 2)
+    is not; the negative off-diagonal mass of the LS row is 2/2 of its diagonal."""
+    g = _golden("worked_example_1d.json")
+    cols = np.array([[0, 1, 2, 3, 4], [0, 1, 2, 3, 4]])
+    vals = np.array([g["mvgd_row_at_h_eq_k_times_35k2"], g["ls_row_times_7k2"]], dtype=float)
+    per, tot = oracle_mod.row_stats([2, 2], cols, vals)
+    assert list(per["m_row"]) == [True, False]
+    assert per["ratio"][0] == 0.0 and per["ratio"][1] == 1.0
+    assert tot["n_offdiag_negative"] == 2 and tot["n_diag_negative"] == 2
+    # a zero diagonal gives NaN and is left out of the means
+    per, tot = oracle_mod.row_stats([0], [[0, 1]], [[0.0, -1.0]])
+    assert np.isnan(per["ratio"][0]) and tot["mean_ratio"] == 0.0 and not per["m_row"][0]
+
+
+@pytest.mark.parametrize("r,inside", [(0.5, False), (0.7, True), (2.0, True), (4.7, True),
+                                      (5.0, False)])
+def test_row_stats_follow_the_m_matrix_window(oracle_mod, r, inside):
+    k = 0.5
+    p = clouds.line_example(k, 2)
+    cols, vals = oracle_mod.rows(p, 4, rows=[2], d=1, h_override=k * np.sqrt(r))
+    per, _ = oracle_mod.row_stats([2], cols, vals)
+    assert bool(per["m_row"][0]) == inside
+    assert (per["ratio"][0] == 0.0) == inside
+
+
+@pytest.mark.parametrize("cloud", ["sphere", "torus"])
+def test_centre_modification_reduces_negative_mass(oracle_mod, cloud):
+    """On curved surfaces the MVGD rows carry far less negative off-diagonal mass than the
+    plain least-squares rows, and with the paper's MLS weights most MVGD rows are M-rows while
+    almost no LS rows are."""
+    cl = clouds.sphere(2000, 1, 20) if cloud == "sphere" else clouds.torus(6000, 2, 24)
+    ids = np.arange(cl.n_points)
+    tot = {}
+    for var in ("mvgd", "ls"):
+        for w in (1.0, 1.0 / cl.k):
+            c, v = oracle_mod.rows(cl.points, cl.k, variant=var, weight_nbr=w)
+            tot[var, w] = oracle_mod.row_stats(ids, c, v)[1]
+    w = 1.0 / cl.k
+    assert tot["mvgd", 1.0]["mean_ratio"] < 0.1 * tot["ls", 1.0]["mean_ratio"]
+    assert tot["mvgd", w]["n_m_rows"] > 0.3 * cl.n_points
+    assert tot["ls", w]["n_m_rows"] < 0.01 * cl.n_points

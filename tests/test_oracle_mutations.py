@@ -40,6 +40,10 @@ MUTANTS = {
     "eigenvalues ascending": ("if (A[order[b]][order[b]] > A[order[a]][order[a]]) {",
                               "if (A[order[b]][order[b]] < A[order[a]][order[a]]) {"),
     "monomial index": ("row[4] = xi * eta;", "row[4] = xi * xi;"),
+    "weighted row not rescaled": ("s->w[r] *= sw;", "s->w[r] *= 1.0;"),
+    "weighted data not rescaled": ("z[k * 3 + c] * sw : z[k * 3 + c]", "z[k * 3 + c] : z[k * 3 + c]"),
+    "weight on the centre row": ("if (r > 0 && pr->w_nbr != 1.0)", "if (pr->w_nbr != 1.0)"),
+    "weight not square-rooted": ("const double sw = sqrt(pr->w_nbr);", "const double sw = pr->w_nbr;"),
 }
 NOOP = ("xi = u[(r - 1) * 2] * ih;", "xi = u[(r - 1) * 2] * ih + 0.0;")
 
