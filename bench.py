@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--workload", default="flat_torus4_1m")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the LS / MLS variant timings and row statistics")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -219,6 +221,29 @@ def main():
               file=sys.stderr, flush=True)
         del P64, f64
 
+    # ---------------- discretisation variants and their row sign statistics ----------------
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        for name, vf in (("mvgd", 0), ("ls", mv.MVGD_FLAG_LS), ("mvgd_mls", mv.MVGD_FLAG_MLS),
+                         ("ls_mls", mv.MVGD_FLAG_LS | mv.MVGD_FLAG_MLS)):
+            tv, tkv, _ = run_gpu(mv, torch, P32, f32, k, 3, 1, flags | vf, offsets)
+            L = mv.mvgd_assemble(P32, k, flags=vf, cloud_offsets=offsets)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = mv.mvgd_row_stats(L)
+            t_rs = time.perf_counter() - t0
+            mv.mvgd_free(L)
+            variants[name] = {"ms_per_step": tv * 1e3,
+                              "assemble_kernel_ms": float(np.mean([t["assemble_ms"] for t in tkv])),
+                              "m_row_fraction": rs["n_m_rows"] / rs["n_rows"],
+                              "mean_neg_ratio": rs["mean_ratio"], "max_neg_ratio": rs["max_ratio"],
+                              "diag_negative_fraction": rs["n_diag_negative"] / rs["n_rows"],
+                              "row_stats_call_ms": t_rs * 1e3}
+            print(f"[bench] variant {name}: {tv * 1e3:.3f} ms/step, M-rows "
+                  f"{rs['n_m_rows']}/{rs['n_rows']}, mean neg ratio {rs['mean_ratio']:.4f}",
+                  file=sys.stderr, flush=True)
+
     # ---------------- accuracy against the FP64 oracle + CPU baseline ----------------
     acc, cpu = {}, None
     y32n = y32.cpu().numpy().astype(np.float64).reshape(n, -1)[:, 0]
@@ -277,6 +302,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": fp64,
+        "variants_fp32": variants,
         "kernels_ms": {"bin": bin32, "assemble": asm32, "apply": app32},
         "accuracy": acc,
         "kernel_source_hash": kernel_source_hash(),

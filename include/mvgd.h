@@ -55,8 +55,12 @@ enum {
                                        of the fitted quadratic at p_i, no centre modification */
     MVGD_FLAG_H_OVERRIDE = 1u << 1, /* use params.h_override as the grid spacing of every row */
     MVGD_FLAG_KEEP_DIAG = 1u << 2,  /* keep per-row h and status bits for mvgd_row_diag */
-    MVGD_FLAG_TIME = 1u << 3        /* record HIP events around the kernel groups of assemble
+    MVGD_FLAG_TIME = 1u << 3,       /* record HIP events around the kernel groups of assemble
                                        and apply on the caller's stream (see mvgd_timing) */
+    MVGD_FLAG_MLS = 1u << 4         /* weighted least squares in both fits: weight 1 at p_i and
+                                       1/K at every neighbour (the moving-least-squares weights
+                                       of the comparison method, Sec. 4); with MVGD_FLAG_LS this
+                                       is that method, without it the MVGD rows on those fits */
 };
 
 typedef struct {
@@ -181,6 +185,32 @@ mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t);
 
 /* mvgd_info -- sizes and counters; waits for the handle's stream (synchronous). */
 mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info);
+
+/*
+ * mvgd_row_stats -- sign statistics of the rows of L (Sec. 3.2: the centre modification is
+ * meant to give off-diagonal entries the sign opposite to the negative diagonal, so that -L is
+ * an M-matrix; plain least-squares rows have entries of mixed sign).
+ *
+ * Per row, with d the diagonal weight and o_j the off-diagonal weights in ascending column
+ * order, each promoted to double: neg_mass = sum_j max(0, -o_j) (one addition per entry, in
+ * that order); ratio = neg_mass / |d| (NaN where d == 0; a row summing to zero is diagonally
+ * dominant exactly when its ratio is 0); an M-row has d < 0 and every o_j >= 0.
+ *
+ * ratio  device double[n_rows] in the caller's point order, or NULL.
+ * out    host; filled after the work on `stream` has finished (the call waits for it).
+ * The mean is over rows with d != 0, reduced in a fixed order (run-to-run reproducible).
+ */
+typedef struct {
+    int64_t n_rows;
+    int64_t n_diag_negative;    /* rows with d < 0 */
+    int64_t n_m_rows;           /* rows with d < 0 and every off-diagonal weight >= 0 */
+    int64_t n_offdiag_negative; /* off-diagonal weights < 0, over all rows */
+    int64_t n_zero_diagonal;    /* rows with d == 0 (degenerate rows) */
+    double mean_ratio;
+    double max_ratio;
+} mvgd_row_stats_t;
+
+mvgd_status mvgd_row_stats(mvgd_matrix *L, double *ratio, mvgd_row_stats_t *out, void *stream);
 
 /* mvgd_pool_trim -- device memory of the current device that the library keeps cached. Handles
  * and assembly scratch come from a stream-ordered pool owned by the library, one per device; freed

@@ -24,8 +24,11 @@
 // Cholesky in FP64; fits of the normal coordinates (Eq. poly); inverse metric G and drift q
 // of the fitted graph (Eq. metric, Eq. eqn3); ell = (tau, -q1, -q2, 2G11, 2G12, 2G22),
 // tau = 2 (G11 + G22)/h^2 (centre value U_i in the virtual-grid differences, Eq. centered1);
-// y = Gram^-1 D ell; w = V y, w_centre -= tau. In FP64 mode the surface fits and y each get one
-// refinement step whose residual is formed from V itself (accuracy O(kappa(V) u), as a QR).
+// y = Gram^-1 D ell; w = W V y, w_centre -= tau. W holds the least-squares weights: 1 at p_i
+// and w_nbr at every neighbour (1: unweighted; 1/K: the moving-least-squares weights of the
+// comparison method in Sec. 4), and the Gram matrix is V^T W V. In FP64 mode the surface fits
+// and y each get one refinement step whose residual is formed from V itself (accuracy
+// O(kappa(V) u), as a QR).
 #pragma once
 
 #include "common.hpp"
@@ -45,6 +48,7 @@ struct AsmParams {
     int64_t groups_per_xcd;     // XCD-aware remap of workgroups to groups
     int32_t variant;            // 0 = MVGD, 1 = plain least squares
     int32_t use_h;
+    double w_nbr;               // least-squares weight of every neighbour (p_i: 1)
     double h_override;
     int64_t ld;                 // sliced-ELL leading dimension
     int32_t *ell_col;           // [K+1][ld] sorted positions
@@ -749,7 +753,9 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
     bool degenerate = !(h > 0.0) || !isfinite(h);
     const T ih = degenerate ? (T)0 : (T)(1.0 / h);
 
-    // Gram matrix of the design over {p_i} u N(i) and right-hand sides of the surface fits
+    // Gram matrix of the design over {p_i} u N(i) and right-hand sides of the surface fits,
+    // weighted: V^T W V and V^T W z with W = diag(1, w_nbr, ..., w_nbr)
+    const double wn = P.w_nbr;
     double Gm[21], rz[NC][6];
 #pragma unroll
     for (int t = 0; t < 21; ++t)
@@ -776,19 +782,22 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
             for (int c = 0; c < NC; ++c)
                 z[c] += nf[c][a] * d;
         }
-        double mv[6];
+        double mv[6], wm[6];
         monomials<T>(u0 * ih, u1 * ih, mv);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            wm[i] = wn * mv[i];
 #pragma unroll
         for (int i = 0; i < 6; ++i)
 #pragma unroll
             for (int j = i; j < 6; ++j)
-                Gm[sym6(i, j)] = fma(mv[i], mv[j], Gm[sym6(i, j)]);
+                Gm[sym6(i, j)] = fma(wm[i], mv[j], Gm[sym6(i, j)]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double zc = (double)z[c];
 #pragma unroll
             for (int i = 0; i < 6; ++i)
-                rz[c][i] = fma(mv[i], zc, rz[c][i]);
+                rz[c][i] = fma(wm[i], zc, rz[c][i]);
         }
     }
     double inv_d[6];
@@ -839,6 +848,7 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
 #pragma unroll
                     for (int t = 0; t < 6; ++t)
                         e = fma(-mv[t], rz[c][t], e);
+                    e *= wn;
 #pragma unroll
                     for (int t = 0; t < 6; ++t)
                         res[c][t] = fma(mv[t], e, res[c][t]);
@@ -907,6 +917,7 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
 #pragma unroll
                 for (int t = 0; t < 6; ++t)
                     w = fma(mv[t], y[t], w);
+                w *= wn;
 #pragma unroll
                 for (int t = 0; t < 6; ++t)
                     res[t] = fma(-w, mv[t], res[t]);
@@ -940,6 +951,7 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
 #pragma unroll
             for (int t = 0; t < 6; ++t)
                 w = fma(mv[t], y[t], w);
+            w *= wn;
         }
         P.ell_col[(int64_t)(k + 1) * ld + q] = pos;
         val[(int64_t)(k + 1) * ld + q] = (T)w;

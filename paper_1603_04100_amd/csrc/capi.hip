@@ -19,6 +19,7 @@
 #include "assemble.hpp"
 #include "bin.hpp"
 #include "common.hpp"
+#include "stats.hpp"
 
 using namespace mvgd;
 
@@ -497,6 +498,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.variant = (p.flags & MVGD_FLAG_LS) ? 1 : 0;
     ap.use_h = (p.flags & MVGD_FLAG_H_OVERRIDE) ? 1 : 0;
     ap.h_override = p.h_override;
+    ap.w_nbr = (p.flags & MVGD_FLAG_MLS) ? 1.0 / (double)K : 1.0;
     ap.ld = L->ld;
     ap.ell_col = L->ell_col;
     ap.ell_val = L->ell_val;
@@ -565,7 +567,7 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
     if (p->precision != MVGD_FP64 && p->precision != MVGD_FP32_MIXED)
         return fail(MVGD_EINVAL, "unknown precision %d", p->precision);
     if (p->flags & ~(uint32_t)(MVGD_FLAG_LS | MVGD_FLAG_H_OVERRIDE | MVGD_FLAG_KEEP_DIAG |
-                             MVGD_FLAG_TIME))
+                             MVGD_FLAG_TIME | MVGD_FLAG_MLS))
         return fail(MVGD_EINVAL, "unknown flag bits 0x%x", p->flags);
     if ((p->flags & MVGD_FLAG_H_OVERRIDE) && !(p->h_override > 0.0 && std::isfinite(p->h_override)))
         return fail(MVGD_EINVAL, "h_override must be positive and finite");
@@ -742,6 +744,49 @@ mvgd_status mvgd_info(mvgd_matrix *L, mvgd_info_t *info)
     info->n_subgroups = (int64_t)c[3];
     info->n_streamed = (int64_t)c[4];
     info->n_growths = (int64_t)c[5];
+    return MVGD_OK;
+}
+
+mvgd_status mvgd_row_stats(mvgd_matrix *L, double *ratio, mvgd_row_stats_t *out, void *stream)
+{
+    if (!L || !out)
+        return fail(MVGD_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (ratio && !is_device_pointer(ratio, L->device))
+        return fail(MVGD_EINVAL, "ratio must be device memory of the matrix's device");
+    L->stream = s;
+    const int64_t n = L->n_total;
+    const int64_t rows_per_block = 4 * kStatsThreads;
+    const int n_parts = (int)((n + rows_per_block - 1) / rows_per_block);
+    void *v = nullptr;
+    if (dev_alloc(&v, sizeof(RowStatsPart) * (size_t)(n_parts + 1), s) != hipSuccess)
+        return fail(MVGD_ENOMEM, "device allocation failed (row statistics)");
+    RowStatsPart *parts = (RowStatsPart *)v;
+    if (L->precision == MVGD_FP64)
+        row_stats_kernel<double><<<n_parts, kStatsThreads, 0, s>>>(
+            (const double *)L->ell_val, L->perm, n, L->ld, L->K + 1, rows_per_block, ratio, parts);
+    else
+        row_stats_kernel<float><<<n_parts, kStatsThreads, 0, s>>>(
+            (const float *)L->ell_val, L->perm, n, L->ld, L->K + 1, rows_per_block, ratio, parts);
+    row_stats_final_kernel<<<1, kStatsThreads, 0, s>>>(parts, n_parts);
+    RowStatsPart tot;
+    const mvgd_status st = check_launch("row statistics");
+    const bool ok = st == MVGD_OK &&
+                    hipMemcpyAsync(&tot, parts + n_parts, sizeof tot, hipMemcpyDeviceToHost, s) ==
+                        hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess;
+    (void)hipFreeAsync(v, s);
+    if (!ok)
+        return st != MVGD_OK ? st : fail(MVGD_EDEVICE, "reading the row statistics failed");
+    memset(out, 0, sizeof *out);
+    out->n_rows = n;
+    out->n_diag_negative = (int64_t)tot.n_diag_neg;
+    out->n_m_rows = (int64_t)tot.n_m_rows;
+    out->n_offdiag_negative = (int64_t)tot.n_off_neg;
+    out->n_zero_diagonal = (int64_t)tot.n_zero_diag;
+    const int64_t nz = n - (int64_t)tot.n_zero_diag;
+    out->mean_ratio = nz > 0 ? tot.sum_ratio / (double)nz : 0.0;
+    out->max_ratio = tot.max_ratio;
     return MVGD_OK;
 }
 

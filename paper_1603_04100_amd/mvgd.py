@@ -22,9 +22,11 @@ LIB_PATH = os.path.join(_HERE, "libmvgd.so")
 MVGD_OK, MVGD_EINVAL, MVGD_ENOMEM, MVGD_EDEVICE, MVGD_EUNSUPPORTED = 0, -1, -2, -3, -4
 MVGD_FP64, MVGD_FP32_MIXED = 0, 1
 MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 4, 8
+MVGD_FLAG_MLS = 16
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
-           "mvgd_timing", "mvgd_pool_trim", "mvgd_status_str", "mvgd_last_error", "mvgd_version")
+           "mvgd_timing", "mvgd_row_stats", "mvgd_pool_trim", "mvgd_status_str",
+           "mvgd_last_error", "mvgd_version")
 
 
 class MvgdError(RuntimeError):
@@ -58,6 +60,13 @@ class mvgd_timing_t(ctypes.Structure):
                 ("apply_ms", ctypes.c_float), ("have_apply", ctypes.c_int32)]
 
 
+class mvgd_row_stats_t(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_diag_negative", ctypes.c_int64),
+                ("n_m_rows", ctypes.c_int64), ("n_offdiag_negative", ctypes.c_int64),
+                ("n_zero_diagonal", ctypes.c_int64), ("mean_ratio", ctypes.c_double),
+                ("max_ratio", ctypes.c_double)]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"MVGD HIP library not built: {path} is missing "
@@ -79,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mvgd_timing.restype = i32
     lib.mvgd_info.argtypes = [vp, ctypes.POINTER(mvgd_info_t)]
     lib.mvgd_info.restype = i32
+    lib.mvgd_row_stats.argtypes = [vp, vp, ctypes.POINTER(mvgd_row_stats_t), vp]
+    lib.mvgd_row_stats.restype = i32
     lib.mvgd_pool_trim.argtypes = [ctypes.c_size_t]
     lib.mvgd_pool_trim.restype = i32
     lib.mvgd_status_str.argtypes = [i32]
@@ -218,6 +229,17 @@ def mvgd_timing(L: Matrix) -> dict:
     t = mvgd_timing_t()
     _check(_lib.mvgd_timing(L.handle, ctypes.byref(t)))
     return {name: getattr(t, name) for name, _ in mvgd_timing_t._fields_}
+
+
+def mvgd_row_stats(L: Matrix, ratio: bool = False, stream=None):
+    """Row sign statistics (dict); with ratio=True also the per-row negative off-diagonal mass
+    over |diagonal| (float64 tensor in the caller's order, NaN on zero diagonals)."""
+    r = torch.empty(L.n_rows, dtype=torch.float64, device=L.device) if ratio else None
+    st = mvgd_row_stats_t()
+    _check(_lib.mvgd_row_stats(L.handle, ctypes.c_void_p(r.data_ptr() if ratio else 0),
+                               ctypes.byref(st), ctypes.c_void_p(_stream(stream))))
+    out = {name: getattr(st, name) for name, _ in mvgd_row_stats_t._fields_}
+    return (out, r) if ratio else out
 
 
 def mvgd_pool_trim(keep_bytes: int = 0):

@@ -91,4 +91,7 @@ def test_apply_and_free_accept_null_safely(mv):
     lib = mv._lib
     assert lib.mvgd_apply(None, None, None, 1, None) == -1
     assert lib.mvgd_csr(None, None, None, None, None) == -1
+    st = mv.mvgd_row_stats_t()
+    assert lib.mvgd_row_stats(None, None, ctypes.byref(st), None) == -1
+    assert lib.mvgd_pool_trim(0) in (0, -3)  # -3 (no device) on a host without a GPU
     lib.mvgd_free(None)

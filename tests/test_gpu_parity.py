@@ -46,16 +46,16 @@ def _oracle_points(pts, precision):
     return pts.astype(np.float32).astype(np.float64) if precision == "fp32" else pts
 
 
-def _kappa(pts, rows, cols, dg):
-    """2-norm condition number of each row's design V (centre row, then N(i)), from the
-    oracle's frame and spacing."""
+def _kappa(pts, rows, cols, dg, w_nbr=1.0):
+    """2-norm condition number of each row's (weighted) design W^1/2 V (centre row, then N(i)),
+    from the oracle's frame and spacing."""
     n = pts.shape[1]
     i = np.asarray(rows)
     nb = cols[cols != i[:, None]].reshape(len(i), -1)
     F = dg[:, 6:22].reshape(-1, 4, 4)[:, :2, :n]
     u = np.einsum("rkn,rtn->rkt", pts[nb] - pts[i][:, None, :], F) / dg[:, 0][:, None, None]
     x, y = u[..., 0], u[..., 1]
-    V = np.stack([np.ones_like(x), x, y, x * x, x * y, y * y], -1)
+    V = np.stack([np.ones_like(x), x, y, x * x, x * y, y * y], -1) * np.sqrt(w_nbr)
     V = np.concatenate([np.eye(6)[None, :1, :].repeat(len(i), 0), V], 1)
     s = np.linalg.svd(V, compute_uv=False)
     return s[:, 0] / s[:, -1]
@@ -94,9 +94,11 @@ def _full_case(mv, cl, precision, **kw):
     n = pts.shape[0]
     L, P, rp, col, val, info = _gpu_csr(mv, pts, k, precision, **kw)
     opts = _oracle_points(pts, precision)
-    o_cols, o_vals, dg = oracle.rows(opts, k, diag=True,
-                                     variant="ls" if kw.get("flags", 0) & 1 else "mvgd")
-    kap = _kappa(opts, np.arange(n), o_cols, dg)
+    flags = kw.get("flags", 0)
+    w_nbr = 1.0 / k if flags & mv.MVGD_FLAG_MLS else 1.0
+    o_cols, o_vals, dg = oracle.rows(opts, k, diag=True, weight_nbr=w_nbr,
+                                     variant="ls" if flags & mv.MVGD_FLAG_LS else "mvgd")
+    kap = _kappa(opts, np.arange(n), o_cols, dg, w_nbr)
     rel = _compare_rows(col.reshape(n, k + 1), val.reshape(n, k + 1), o_cols, o_vals,
                         _row_tol(precision, dg, kap))
     assert (rp == np.arange(n + 1) * (k + 1)).all()
@@ -158,6 +160,102 @@ def test_ls_variant_and_h_override(mv):
     _compare_rows(col.cpu().numpy().reshape(-1, 21), val.cpu().numpy().reshape(-1, 21), oc, ov,
                   _row_tol("fp64", dg, _kappa(pts, np.arange(3000), oc, dg)))
     L.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", ["mvgd", "ls"])
+def test_mls_weights(mv, precision, variant):
+    """Weighted fits (1 at p_i, 1/K at the neighbours), with and without the centre term."""
+    cl = clouds.torus(5000, 23, 24) if variant == "mvgd" else clouds.sphere(3000, 24, 20)
+    flags = mv.MVGD_FLAG_MLS | (mv.MVGD_FLAG_LS if variant == "ls" else 0)
+    L, *_ = _full_case(mv, cl, precision, flags=flags)
+    L.free()
+
+
+def _stats_of_export(mv, L, n, k, offs=None):
+    """The row statistics' definition applied to the library's own exported rows (columns are
+    local to each cloud)."""
+    rp, col, val = mv.mvgd_csr(L)
+    col = col.cpu().numpy().reshape(n, k + 1)
+    val = val.cpu().numpy().astype(np.float64).reshape(n, k + 1)
+    offs = [0, n] if offs is None else offs
+    local = np.concatenate([np.arange(b - a) for a, b in zip(offs[:-1], offs[1:])])
+    return oracle.row_stats(local, col, val)
+
+
+@pytest.mark.parametrize("case", ["sphere-mvgd", "sphere-ls", "torus-mls", "batch-fp32",
+                                  "degenerate"])
+def test_row_stats_match_definition(mv, case):
+    """GPU statistics equal the definition evaluated on the same matrix: counts and per-row
+    ratios bit-identical (same order of additions), mean within rounding of the reduction."""
+    offs = None
+    if case.startswith("sphere"):
+        cl = clouds.sphere(3000, 31, 20)
+        P = torch.tensor(cl.points, device=DEV)
+        flags = mv.MVGD_FLAG_LS if case.endswith("ls") else 0
+    elif case == "torus-mls":
+        cl = clouds.torus(6000, 32, 24)
+        P = torch.tensor(cl.points, device=DEV)
+        flags = mv.MVGD_FLAG_MLS
+    elif case == "batch-fp32":
+        cl = clouds.ellipsoid_batch(n_clouds=4, seed=33, k=20, n_min=500, n_max=5000)
+        P = torch.tensor(cl.points.astype(np.float32), device=DEV)
+        offs = [int(v) for v in cl.offsets]
+        flags = mv.MVGD_FLAG_MLS
+    else:
+        rng = np.random.default_rng(34)
+        base = clouds.sphere(1000, 35, 16).points
+        pts = np.concatenate([base, np.repeat(base[:3], 20, 0)])  # clusters of duplicates
+        cl = clouds.Cloud("dups", pts, np.array([0, len(pts)]), 16, None, None, {})
+        P = torch.tensor(pts[rng.permutation(len(pts))], device=DEV)
+        flags = 0
+    n, k = P.shape[0], cl.k
+    L = mv.mvgd_assemble(P, k, flags=flags, cloud_offsets=offs)
+    got, ratio = mv.mvgd_row_stats(L, ratio=True)
+    per, tot = _stats_of_export(mv, L, n, k, offs)
+    for key in ("n_rows", "n_diag_negative", "n_m_rows", "n_offdiag_negative"):
+        assert got[key] == tot[key], key
+    r = ratio.cpu().numpy()
+    assert np.array_equal(np.isnan(r), np.isnan(per["ratio"]))
+    ok = ~np.isnan(r)
+    assert (r[ok] == per["ratio"][ok]).all()
+    assert got["n_zero_diagonal"] == int((~ok).sum())
+    assert got["max_ratio"] == tot["max_ratio"]
+    assert got["mean_ratio"] == pytest.approx(tot["mean_ratio"], rel=1e-12, abs=1e-300)
+    if case == "degenerate":
+        assert got["n_zero_diagonal"] > 0
+    L.free()
+
+
+def test_row_stats_paper_claim_on_the_gpu(mv):
+    """The centre modification cuts the negative off-diagonal mass (FP32-mixed, torus), and with
+    the MLS weights most MVGD rows are M-rows while almost no LS rows are; per-row M decisions
+    agree with the FP64 oracle's wherever the smallest off-diagonal is clear of zero."""
+    cl = clouds.torus(8000, 36, 24)
+    P = torch.tensor(cl.points.astype(np.float32), device=DEV)
+    res = {}
+    for name, flags in (("mvgd", 0), ("ls", mv.MVGD_FLAG_LS), ("mvgd-mls", mv.MVGD_FLAG_MLS),
+                        ("ls-mls", mv.MVGD_FLAG_LS | mv.MVGD_FLAG_MLS)):
+        L = mv.mvgd_assemble(P, 24, flags=flags)
+        res[name] = mv.mvgd_row_stats(L)
+        if name == "mvgd-mls":
+            rp, col, val = mv.mvgd_csr(L)
+            gv = val.cpu().numpy().astype(np.float64).reshape(-1, 25)
+            opts = cl.points.astype(np.float32).astype(np.float64)
+            oc, ov = oracle.rows(opts, 24, weight_nbr=1.0 / 24)
+            ids = np.arange(cl.n_points)
+            g_m = oracle.row_stats(ids, col.cpu().numpy().reshape(-1, 25), gv)[0]["m_row"]
+            o_m = oracle.row_stats(ids, oc, ov)[0]["m_row"]
+            off = np.where(oc == ids[:, None], np.inf, np.abs(ov))
+            clear = off.min(1) > 1e-3 * np.abs(ov).max(1)
+            assert (g_m[clear] == o_m[clear]).all()
+            assert clear.mean() > 0.8
+        L.free()
+    n = cl.n_points
+    assert res["mvgd"]["mean_ratio"] < 0.1 * res["ls"]["mean_ratio"]
+    assert res["mvgd-mls"]["n_m_rows"] > 0.3 * n and res["ls-mls"]["n_m_rows"] < 0.01 * n
+    print(f"\n[row stats torus 8k fp32] " + ", ".join(
+        f"{k}: M-rows {v['n_m_rows']}/{n}, mean ratio {v['mean_ratio']:.4f}" for k, v in res.items()))
 
 
 def test_exact_ties_on_a_lattice(mv):
