@@ -111,6 +111,8 @@ def rows(points, k: int, rows=None, d: int = 2, variant: str = "mvgd", h_overrid
          diag: bool = False, nthreads: int = 0, weight_nbr: float = 1.0):
     """MVGD rows (or the plain LS variant) for the given rows.
 
+    variant: "mvgd" (Eq. center and its 2-D form), "ls" (derivatives of the fit, no centre
+    term) or, for curves only, "div" (the divergence form, Eq. divergence).
     weight_nbr: least-squares weight of every neighbour (p_i has weight 1); 1 is the unweighted
     fit, 1/k the moving-least-squares weights of the paper's comparison (Sec. 4).
     Returns (cols [R, K+1] int64 ascending, vals [R, K+1] float64[, diag [R, 64]]).
@@ -120,7 +122,7 @@ def rows(points, k: int, rows=None, d: int = 2, variant: str = "mvgd", h_overrid
     cols = np.empty((nr, k + 1), dtype=np.int64)
     vals = np.empty((nr, k + 1), dtype=np.float64)
     dg = np.empty((nr, ODIAG), dtype=np.float64) if diag else None
-    var = {"mvgd": 0, "ls": 1}[variant]
+    var = {"mvgd": 0, "ls": 1, "div": 2}[variant]
     use_h = 0 if h_override is None else 1
     rc = _load().oracle_rows(_ptr(p), p.shape[0], p.shape[1], d, k, var, use_h,
                              float(h_override or 0.0), float(weight_nbr), _ptr(r), nr,

@@ -32,6 +32,8 @@
  *       So L_i U = ell^T b - tau U_i, tau = 2 (G11 + G22)/h^2,
  *       ell = (tau, -q1, -q2, 2 G11, 2 G12, 2 G22) on b = (b00, b10, b01, b20, b11, b02).
  *       The plain least-squares variant (Sec. 2) uses ell with tau = 0 and no centre term.
+ *       Curves (d = 1) also have the divergence form (Eq. divergence): the flux
+ *       (1/sqrt g) U_x differenced at +-h/2, with g = 1 + |y'|^2 of the fitted curve.
  *   O10 weights w = V (V^T V)^-1 D ell, D = diag of the h scaling, then w_centre -= tau.
  *       Weighted least squares (the moving-least-squares comparison of Sec. 4, weight 1 at p_i
  *       and w at every neighbour; w = 1/K there): both fits minimise sum_r w_r (residual_r)^2,
@@ -457,6 +459,24 @@ static void mvgd_row(const double *P, int64_t N, const oparams *pr, int64_t i, o
             tau = (pr->variant == 0) ? 2.0 * (G[0] + G[3]) / (h * h) : 0.0;
             ell[0] = tau; ell[1] = -q[0]; ell[2] = -q[1];
             ell[3] = 2.0 * G[0]; ell[4] = 2.0 * G[1]; ell[5] = 2.0 * G[3];
+        } else if (pr->variant == 2) {
+            /* divergence form (Eq. divergence): with s(x) = sqrt(1 + sum_c y_c'(x)^2) of the
+             * fitted curve, a+- = 1 / (h^2 s(0) s(+-h/2)) and
+             * L_i U = a+ U(h) + a- U(-h) - (a+ + a-) U_i, U(+-h) = b0 +- b1 h + b2 h^2. */
+            double s0 = 1.0, sp = 1.0, sm = 1.0;
+            for (int c = 0; c < nc; ++c) {
+                const double a1 = a_unscaled[c * m + 1], a2 = a_unscaled[c * m + 2];
+                const double dp = a1 + 2.0 * a2 * (0.5 * h), dm = a1 - 2.0 * a2 * (0.5 * h);
+                s0 += a1 * a1;
+                sp += dp * dp;
+                sm += dm * dm;
+            }
+            s0 = sqrt(s0);
+            sp = sqrt(sp);
+            sm = sqrt(sm);
+            const double ap = 1.0 / (h * h * s0 * sp), am = 1.0 / (h * h * s0 * sm);
+            tau = ap + am;
+            ell[0] = tau; ell[1] = (ap - am) * h; ell[2] = tau * h * h;
         } else {
             tau = (pr->variant == 0) ? 2.0 * G[0] / (h * h) : 0.0;
             ell[0] = tau; ell[1] = -q[0]; ell[2] = 2.0 * G[0];
@@ -564,7 +584,8 @@ int oracle_knn(const double *P, int64_t N, int n, int K, const int64_t *rows, in
     return 0;
 }
 
-/* MVGD (variant 0) or plain LS (variant 1) rows for the listed rows (rows == NULL: all), with
+/* MVGD (variant 0), plain LS (variant 1) or, for curves (d = 1), MVGD in the divergence form
+ * (variant 2) rows for the listed rows (rows == NULL: all), with
  * least-squares weight w_nbr (> 0) on every neighbour and 1 on p_i (w_nbr = 1: unweighted).
  * out_cols / out_vals: nrows x (K+1), columns ascending. out_diag: nrows x 64 or NULL.
  * Returns 0, -1 on bad arguments, -2 on non-finite coordinates. */
@@ -575,7 +596,8 @@ int oracle_rows(const double *P, int64_t N, int n, int d, int K, int variant, in
     int rc = check_common(P, N, n, d, K);
     if (rc)
         return rc;
-    if ((variant != 0 && variant != 1) || !(w_nbr > 0.0) || !isfinite(w_nbr))
+    if (variant < 0 || variant > 2 || (variant == 2 && d != 1) || !(w_nbr > 0.0) ||
+        !isfinite(w_nbr))
         return -1;
     oparams pr = {n, d, K, variant, use_h, h_override, w_nbr};
     int64_t R = rows ? nrows : N;

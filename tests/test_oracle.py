@@ -413,6 +413,10 @@ def _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod, variant="mvgd", w_
         Dxy = (Uh(h, h) - Uh(h, -h) - Uh(-h, h) + Uh(-h, -h)) / (4 * h * h)
         return G[0, 0] * Dxx + 2 * G[0, 1] * Dxy + G[1, 1] * Dyy - q[0] * Dx - q[1] * Dy
     Uh = lambda x: (mono(np.array([x])) @ b)[0]
+    if variant == "div":  # Eq. divergence with the fitted curve's slope at 0 and +-h/2
+        s = lambda x: np.sqrt(1.0 + sum((ac[1] + 2 * ac[2] * x) ** 2 for ac in a))
+        return (Uh(h) / s(h / 2) - (1 / s(h / 2) + 1 / s(-h / 2)) * U[0]
+                + Uh(-h) / s(-h / 2)) / (h * h * s(0))
     Dx = (Uh(h) - Uh(-h)) / (2 * h)
     Dxx = (Uh(h) - 2 * Ui + Uh(-h)) / h ** 2
     return G[0, 0] * Dxx - q[0] * Dx
@@ -422,7 +426,8 @@ def _virtual_grid_value(P, i, nb, frame, h, d, U, oracle_mod, variant="mvgd", w_
     ("sphere", "mvgd", False), ("torus", "mvgd", False), ("flat4", "mvgd", False),
     ("circle", "mvgd", False), ("helix", "mvgd", False),
     ("sphere", "ls", False), ("flat4", "ls", True), ("torus", "mvgd", True),
-    ("helix", "ls", True), ("circle", "mvgd", True)])
+    ("helix", "ls", True), ("circle", "mvgd", True),
+    ("circle", "div", False), ("helix", "div", False), ("helix", "div", True)])
 def test_rows_equal_virtual_grid_definition(oracle_mod, which, variant, weighted):
     rng = np.random.default_rng(7)
     if which == "sphere":
@@ -454,16 +459,36 @@ def test_rows_equal_virtual_grid_definition(oracle_mod, which, variant, weighted
             assert ours == pytest.approx(ref, rel=1e-9, abs=1e-11 * np.abs(vals[r]).sum())
 
 
-def test_circle_converges(oracle_mod):
-    """Unit circle, Delta sin(2t) = -4 sin(2t) (Sec. 4.2): the d = 1 path converges."""
+@pytest.mark.parametrize("variant", ["mvgd", "div"])
+def test_circle_converges(oracle_mod, variant):
+    """Unit circle, Delta sin(2t) = -4 sin(2t) (Sec. 4.2): both curve forms converge."""
     errs = []
     for n in (500, 2000, 8000):
         t = np.random.default_rng(n).uniform(0, 2 * np.pi, n)
         P = np.stack([np.cos(t), np.sin(t)], 1)
-        rp, c, v = oracle_mod.assemble(P, 6, d=1)
+        rp, c, v = oracle_mod.assemble(P, 6, d=1, variant=variant)
         e = oracle_mod.apply(rp, c, v, np.sin(2 * t)) + 4 * np.sin(2 * t)
         errs.append(np.sqrt((e ** 2).mean()))
+        rs = v.reshape(n, 7).sum(1)
+        assert np.abs(rs).max() <= 1e-12 * np.abs(v).reshape(n, 7).sum(1).max()
     assert errs[0] / errs[2] > 4.0, errs
+
+
+def test_divergence_form_on_straight_lines(oracle_mod):
+    """On a straight line the fitted slope is constant, s(x) = s(0), and the divergence form is
+    the centred form: identical rows (the printed 1-D row at h = k included)."""
+    g = _golden("worked_example_1d.json")
+    p = clouds.line_example(0.3, 3, direction=[1.0, 2.0, -0.5], offset=[0.1, 0.2, 0.3])
+    _, v_div = oracle_mod.rows(p, 4, rows=[2], d=1, variant="div")
+    want = np.array(g["mvgd_row_at_h_eq_k_times_35k2"]) / (35.0 * 0.09)
+    np.testing.assert_allclose(v_div[0], want, rtol=0, atol=1e-12 * np.abs(want).max())
+    t = np.sort(np.random.default_rng(3).uniform(-5, 5, 300))
+    P = t[:, None] * np.array([[0.6, -0.8]]) + np.array([[2.0, 1.0]])
+    _, v1 = oracle_mod.rows(P, 8, d=1, variant="mvgd")
+    _, v2 = oracle_mod.rows(P, 8, d=1, variant="div")
+    np.testing.assert_allclose(v2, v1, rtol=0, atol=1e-10 * np.abs(v1).max())
+    with pytest.raises(ValueError):
+        oracle_mod.rows(clouds.sphere(200, 0, 10).points, 10, variant="div")
 
 
 # ----------------------------------------------------------------------------------------

@@ -44,6 +44,9 @@ MUTANTS = {
     "weighted data not rescaled": ("z[k * 3 + c] * sw : z[k * 3 + c]", "z[k * 3 + c] : z[k * 3 + c]"),
     "weight on the centre row": ("if (r > 0 && pr->w_nbr != 1.0)", "if (pr->w_nbr != 1.0)"),
     "weight not square-rooted": ("const double sw = sqrt(pr->w_nbr);", "const double sw = pr->w_nbr;"),
+    "divergence flux at +-h": ("dp = a1 + 2.0 * a2 * (0.5 * h)", "dp = a1 + 2.0 * a2 * h"),
+    "divergence without s(0)": ("ap = 1.0 / (h * h * s0 * sp)", "ap = 1.0 / (h * h * sp)"),
+    "divergence drift sign": ("ell[1] = (ap - am) * h;", "ell[1] = (am - ap) * h;"),
 }
 NOOP = ("xi = u[(r - 1) * 2] * ih;", "xi = u[(r - 1) * 2] * ih + 0.0;")
 
