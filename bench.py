@@ -99,7 +99,7 @@ def run_unbatched(mv, torch, P, f, k, offsets, flags):
 def cpu_baseline(oracle, pts64, k, target_s: float, max_rows: int):
     n = pts64.shape[0]
     rng = np.random.default_rng(123)
-    probe = rng.choice(n, min(64, n), replace=False)
+    probe = rng.choice(n, min(512, n), replace=False)
     t = time.perf_counter()
     oracle.rows(pts64, k, rows=probe)
     per_row = (time.perf_counter() - t) / probe.shape[0]

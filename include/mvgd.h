@@ -57,16 +57,19 @@ enum {
     MVGD_FLAG_KEEP_DIAG = 1u << 2,  /* keep per-row h and status bits for mvgd_row_diag */
     MVGD_FLAG_TIME = 1u << 3,       /* record HIP events around the kernel groups of assemble
                                        and apply on the caller's stream (see mvgd_timing) */
-    MVGD_FLAG_MLS = 1u << 4         /* weighted least squares in both fits: weight 1 at p_i and
+    MVGD_FLAG_MLS = 1u << 4,        /* weighted least squares in both fits: weight 1 at p_i and
                                        1/K at every neighbour (the moving-least-squares weights
                                        of the comparison method, Sec. 4); with MVGD_FLAG_LS this
                                        is that method, without it the MVGD rows on those fits */
+    MVGD_FLAG_DIVERGENCE = 1u << 5  /* curves only (d = 1), not with MVGD_FLAG_LS: the
+                                       divergence form of Eq. divergence instead of Eq. center */
 };
 
 typedef struct {
-    int32_t n_ambient;  /* n: 3 or 4 */
-    int32_t d_manifold; /* d: 2 (1 is reserved for curves and returns MVGD_EUNSUPPORTED) */
-    int32_t k;          /* K nearest neighbours: 5 <= K <= 63 and K < points in every cloud */
+    int32_t n_ambient;  /* n: 3 or 4 for surfaces, 2 or 3 for curves */
+    int32_t d_manifold; /* d: 2 (surfaces) or 1 (curves) */
+    int32_t k;          /* K nearest neighbours: 5 <= K <= 63 for surfaces, 2 <= K <= 63 for
+                           curves, and K < points in every cloud */
     int32_t precision;  /* mvgd_precision */
     uint32_t flags;     /* MVGD_FLAG_* */
     double h_override;  /* > 0, used only with MVGD_FLAG_H_OVERRIDE */
@@ -110,7 +113,9 @@ typedef struct {
  * (Eq. DefH); least-squares quadratic fits over {p_i} u N(i) of each normal coordinate
  * (Eq. poly) and of U (Eq. T); metric of the fitted graph (Eq. metric) giving the coefficients of
  * Eq. eqn3; central differences on the virtual grid of spacing h with U_i at the centre node
- * (Eq. centered1 and its higher-dimensional form).
+ * (Eq. centered1 and its higher-dimensional form). Curves (d = 1): one tangent axis, monomials
+ * (1, xi, xi^2), h from Eq. DefH, Eq. LB1 with Eq. center, or Eq. divergence with
+ * MVGD_FLAG_DIVERGENCE.
  *
  * points        device, row-major [n_total, n_ambient]; float for MVGD_FP32_MIXED, double for
  *               MVGD_FP64. Must be finite (non-finite values give MVGD_EINVAL).

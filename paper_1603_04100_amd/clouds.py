@@ -10,6 +10,7 @@ remaining surfaces are synthetic stand-ins of the same kind, since the paper's p
 are not available):
 
 * ``sphere``           unit sphere in R^3, normalised standard Gaussian (uniform density).
+* ``circle``, ``helix`` curves (d = 1): the unit circle of Sec. 4.2 and an open helix in R^3.
 * ``torus``            torus in R^3 with tube-angle density proportional to 1 + 0.5 cos(theta).
 * ``ellipsoid_batch``  many ellipsoids of log-uniform size (batched assembly).
 * ``flat_torus4``      flat torus (cos t, sin t, cos p, sin p) in R^4 plus Gaussian noise.
@@ -32,7 +33,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Cloud", "sphere", "torus", "ellipsoid_batch", "flat_torus4", "serving_stream",
+    "Cloud", "sphere", "circle", "helix", "torus", "ellipsoid_batch", "flat_torus4", "serving_stream",
     "random_plane", "line_example", "sphere_harmonic", "implicit_laplacian",
     "ellipsoid_functions", "config", "CONFIGS",
 ]
@@ -97,6 +98,35 @@ def sphere(n: int = 2000, seed: int = 1, k: int = 20, degrees=(1,)) -> Cloud:
     f = np.stack([sphere_harmonic(p, l) for l in degrees], axis=1)
     lap = np.stack([-l * (l + 1) * sphere_harmonic(p, l) for l in degrees], axis=1)
     return _single("sphere", p, k, f, lap, seed=seed, degrees=list(degrees))
+
+
+# ----------------------------------------------------------------------------------------
+# curves (d = 1)
+# ----------------------------------------------------------------------------------------
+def circle(n: int = 4000, seed: int = 6, k: int = 6, sampling: str = "random") -> Cloud:
+    """Unit circle in R^2 (Sec. 4.2). sampling: "uniform" (equispaced angles, rotated by a random
+    offset) or "random" (angles ~ U[0, 2pi)). f = sin(2t), Delta f = -4 sin(2t); the paper's
+    solve uses U = -sin(2t) with -Delta U = -4 sin(2t)."""
+    rng = np.random.default_rng(seed)
+    if sampling == "uniform":
+        t = rng.uniform(0.0, 2.0 * np.pi) + 2.0 * np.pi * np.arange(n) / n
+    else:
+        t = rng.uniform(0.0, 2.0 * np.pi, n)
+    p = np.stack([np.cos(t), np.sin(t)], axis=1)
+    return _single("circle", p, k, np.sin(2 * t), -4.0 * np.sin(2 * t), seed=seed,
+                   sampling=sampling, d=1)
+
+
+def helix(n: int = 4000, seed: int = 7, k: int = 8, pitch: float = 0.3,
+          turns: float = 2.0) -> Cloud:
+    """Helix (cos t, sin t, pitch t), t ~ U[0, 2pi turns) (an open curve). Arclength
+    s = t sqrt(1 + pitch^2); f = sin(2t), Delta f = d^2 f / ds^2 = -4 sin(2t) / (1 + pitch^2)
+    (the rows near the two ends see one-sided neighbourhoods)."""
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.0, 2.0 * np.pi * turns, n)
+    p = np.stack([np.cos(t), np.sin(t), pitch * t], axis=1)
+    return _single("helix", p, k, np.sin(2 * t), -4.0 * np.sin(2 * t) / (1.0 + pitch ** 2),
+                   seed=seed, pitch=pitch, turns=turns, d=1)
 
 
 # ----------------------------------------------------------------------------------------
@@ -288,6 +318,7 @@ CONFIGS = {
     "torus_200k": dict(fn=torus, kw=dict(n=200_000, seed=2, k=24)),
     "ellipsoids_256": dict(fn=ellipsoid_batch, kw=dict(n_clouds=256, seed=3, k=20)),
     "flat_torus4_1m": dict(fn=flat_torus4, kw=dict(n=1_000_000, seed=4, k=32)),
+    "circle_100k": dict(fn=circle, kw=dict(n=100_000, seed=6, k=6)),
 }
 
 

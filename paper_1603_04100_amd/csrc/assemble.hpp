@@ -17,9 +17,10 @@
 //   slow    lanes whose boundary overflows (exact ties, extreme clustering) extract the missing
 //           neighbours one at a time by (key, index) over repeated streams.
 //
-// Fit (per lane, Sec. 2 and Sec. 3.1): covariance of N(i) about its barycentre accumulated in
-// FP64 from exact differences; cyclic Jacobi in FP64 (frame: the two largest eigenvalues are
-// tangent, the rest normal); local coordinates and the spacing h = 1/4 min tangent range
+// Fit (per lane, Sec. 2 and Sec. 3.1; surfaces d = 2 and curves d = 1): covariance of N(i)
+// about its barycentre accumulated in FP64 from exact differences; cyclic Jacobi in FP64 (frame:
+// the d largest eigenvalues are tangent, the rest normal); local coordinates and the spacing
+// h = 1/4 min tangent range
 // (Eq. DefH); design monomials of (u/h) over {p_i} u N(i); Gram matrix accumulated in FP64;
 // Cholesky in FP64; fits of the normal coordinates (Eq. poly); inverse metric G and drift q
 // of the fitted graph (Eq. metric, Eq. eqn3); ell = (tau, -q1, -q2, 2G11, 2G12, 2G22),
@@ -46,7 +47,7 @@ struct AsmParams {
     int32_t K;
     int64_t n_groups;
     int64_t groups_per_xcd;     // XCD-aware remap of workgroups to groups
-    int32_t variant;            // 0 = MVGD, 1 = plain least squares
+    int32_t variant;            // 0 = MVGD, 1 = plain least squares, 2 = divergence form (d=1)
     int32_t use_h;
     double w_nbr;               // least-squares weight of every neighbour (p_i: 1)
     double h_override;
@@ -91,6 +92,12 @@ template <typename T, int NA>
 __device__ __forceinline__ float cull_dist(const Pt<T> &q, const Pt<T> &c);
 
 template <>
+__device__ __forceinline__ float cull_dist<float, 2>(const Pt<float> &q, const Pt<float> &c)
+{
+    float d0 = c.v[0] - q.v[0], d1 = c.v[1] - q.v[1];
+    return fmaf(d1, d1, d0 * d0);
+}
+template <>
 __device__ __forceinline__ float cull_dist<float, 3>(const Pt<float> &q, const Pt<float> &c)
 {
     float d0 = c.v[0] - q.v[0], d1 = c.v[1] - q.v[1], d2 = c.v[2] - q.v[2];
@@ -101,6 +108,11 @@ __device__ __forceinline__ float cull_dist<float, 4>(const Pt<float> &q, const P
 {
     float d0 = c.v[0] - q.v[0], d1 = c.v[1] - q.v[1], d2 = c.v[2] - q.v[2], d3 = c.v[3] - q.v[3];
     return fmaf(d3, d3, fmaf(d2, d2, fmaf(d1, d1, d0 * d0)));
+}
+template <>
+__device__ __forceinline__ float cull_dist<double, 2>(const Pt<double> &q, const Pt<double> &c)
+{
+    return (float)exact_key<double, 2>(q, c);
 }
 template <>
 __device__ __forceinline__ float cull_dist<double, 3>(const Pt<double> &q, const Pt<double> &c)
@@ -262,81 +274,466 @@ __device__ __forceinline__ void jacobi_eig(double A[N][N], double W[N][N])
     }
 }
 
-// packed upper triangle of a 6x6 symmetric matrix: index of (i, j), i <= j
-__host__ __device__ constexpr int sym6(int i, int j)
+// =============================================================================================
+// per-lane fit: frame, spacing, least-squares fits, coefficients and the row (d = 1 or 2)
+// =============================================================================================
+template <int D> struct FitShape {
+    static constexpr int M = (D == 2) ? 6 : 3;  // monomials of degree <= 2 in D variables
+    static constexpr int NG = M * (M + 1) / 2;  // packed Gram entries
+};
+
+// packed upper triangle of an M x M symmetric matrix: index of (i, j), i <= j
+template <int M>
+__host__ __device__ constexpr int symM(int i, int j)
 {
-    return i * 6 - i * (i - 1) / 2 + (j - i);
+    return i * M - i * (i - 1) / 2 + (j - i);
 }
 
-// In-place Cholesky G = L L^T (L stored in the same packed slots, L(j,i) at sym6(i,j)).
-// Returns false when a pivot is not positive or min L_ii < 1e-6 max L_ii.
-__device__ __forceinline__ bool chol6(double G[21], double inv_diag[6])
+// In-place Cholesky G = L L^T (L(j,i) stored at symM(i,j)). Returns false when a pivot is not
+// positive or min L_ii < 1e-6 max L_ii.
+template <int M>
+__device__ __forceinline__ bool chol_packed(double G[M * (M + 1) / 2], double inv_diag[M])
 {
     double dmin = INFINITY, dmax = 0.0;
     bool ok = true;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double s = G[sym6(i, i)];
+    for (int i = 0; i < M; ++i) {
+        double s = G[symM<M>(i, i)];
 #pragma unroll
         for (int k = 0; k < i; ++k)
-            s -= G[sym6(k, i)] * G[sym6(k, i)];
+            s -= G[symM<M>(k, i)] * G[symM<M>(k, i)];
         ok = ok && (s > 0.0);
         const double lii = sqrt(s > 0.0 ? s : 0.0);
-        G[sym6(i, i)] = lii;
+        G[symM<M>(i, i)] = lii;
         inv_diag[i] = lii > 0.0 ? 1.0 / lii : 0.0;
         dmin = fmin(dmin, lii);
         dmax = fmax(dmax, lii);
 #pragma unroll
-        for (int j = i + 1; j < 6; ++j) {
-            double t = G[sym6(i, j)];
+        for (int j = i + 1; j < M; ++j) {
+            double t = G[symM<M>(i, j)];
 #pragma unroll
             for (int k = 0; k < i; ++k)
-                t -= G[sym6(k, j)] * G[sym6(k, i)];
-            G[sym6(i, j)] = t * inv_diag[i]; // L(j, i)
+                t -= G[symM<M>(k, j)] * G[symM<M>(k, i)];
+            G[symM<M>(i, j)] = t * inv_diag[i];
         }
     }
     return ok && (dmin >= 1e-6 * dmax) && isfinite(dmax);
 }
 
 // solve (L L^T) x = b in place
-__device__ __forceinline__ void chol6_solve(const double L[21], const double inv_diag[6], double b[6])
+template <int M>
+__device__ __forceinline__ void chol_packed_solve(const double L[M * (M + 1) / 2],
+                                                  const double inv_diag[M], double b[M])
 {
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
+    for (int i = 0; i < M; ++i) {
         double s = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k)
-            s -= L[sym6(k, i)] * b[k];
+            s -= L[symM<M>(k, i)] * b[k];
         b[i] = s * inv_diag[i];
     }
 #pragma unroll
-    for (int i = 5; i >= 0; --i) {
+    for (int i = M - 1; i >= 0; --i) {
         double s = b[i];
 #pragma unroll
-        for (int k = i + 1; k < 6; ++k)
-            s -= L[sym6(i, k)] * b[k];
+        for (int k = i + 1; k < M; ++k)
+            s -= L[symM<M>(i, k)] * b[k];
         b[i] = s * inv_diag[i];
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void monomials(T xi, T eta, double m[6])
+// design monomials of the scaled local coordinates: (1, xi, eta, xi^2, xi eta, eta^2) for
+// surfaces, (1, xi, xi^2) for curves (products formed in T, widened to double)
+template <typename T, int D>
+__device__ __forceinline__ void monomials(const T u[D], T ih, double m[FitShape<D>::M])
 {
+    const T xi = u[0] * ih;
     m[0] = 1.0;
     m[1] = (double)xi;
-    m[2] = (double)eta;
-    m[3] = (double)(xi * xi);
-    m[4] = (double)(xi * eta);
-    m[5] = (double)(eta * eta);
+    if constexpr (D == 2) {
+        const T eta = u[1] * ih;
+        m[2] = (double)eta;
+        m[3] = (double)(xi * xi);
+        m[4] = (double)(xi * eta);
+        m[5] = (double)(eta * eta);
+    } else {
+        m[2] = (double)(xi * xi);
+    }
+}
+
+// local coordinates of p_j - p_i: tangent u (D) and normal z (NA - D)
+template <typename T, int NA, int D>
+__device__ __forceinline__ void local_coords(const Pt<T> &pj, const Pt<T> &qp,
+                                             const T tf[D][NA], const T nf[NA - D][NA], T u[D],
+                                             T z[NA - D])
+{
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        u[t] = 0;
+#pragma unroll
+    for (int c = 0; c < NA - D; ++c)
+        z[c] = 0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        const T d = pj.v[a] - qp.v[a];
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            u[t] += tf[t][a] * d;
+#pragma unroll
+        for (int c = 0; c < NA - D; ++c)
+            z[c] += nf[c][a] * d;
+    }
+}
+
+template <typename T, int NA, int D>
+__device__ __forceinline__ void fit_row(const AsmParams &P, const Pt<T> *spts,
+                                        const int32_t *list, int lane, int q, const Pt<T> &qp,
+                                        bool slow_row)
+{
+    constexpr int NC = NA - D; // normal coordinates
+    constexpr int M = FitShape<D>::M;
+    constexpr int NG = FitShape<D>::NG;
+    const int K = P.K;
+    T *val = (T *)P.ell_val;
+    double qd[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        qd[a] = (double)qp.v[a];
+
+    // covariance about the barycentre of N(i) (p_i excluded), FP64 from exact differences
+    double s1[NA], s2[NA][NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        s1[a] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c)
+            s2[a][c] = 0.0;
+    }
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+        const Pt<T> pj = spts[list[k * kWave + lane]];
+        double dv[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            dv[a] = (double)pj.v[a] - qd[a];
+            s1[a] += dv[a];
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int c = a; c < NA; ++c)
+                s2[a][c] = fma(dv[a], dv[c], s2[a][c]);
+    }
+    const double invK = 1.0 / (double)K;
+    double A[NA][NA], W[NA][NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int c = a; c < NA; ++c) {
+            A[a][c] = s2[a][c] - s1[a] * s1[c] * invK;
+            A[c][a] = A[a][c];
+        }
+    jacobi_eig<NA>(A, W);
+    double lam[NA];
+    int rank[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        lam[a] = A[a][a];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        rank[a] = 0;
+#pragma unroll
+        for (int c = 0; c < NA; ++c)
+            rank[a] += (c != a) && (lam[c] > lam[a] || (lam[c] == lam[a] && c < a));
+    }
+    // frame: the D largest eigenvalues' vectors are tangent, the rest normal
+    T tf[D][NA], nf[NC][NA];
+    double lam_t[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+        lam_t[t] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+#pragma unroll
+        for (int t = 0; t < D; ++t)
+            if (rank[a] == t)
+                lam_t[t] = lam[a];
+#pragma unroll
+        for (int r = 0; r < NA; ++r) {
+            const T v = (T)W[r][a];
+#pragma unroll
+            for (int t = 0; t < D; ++t)
+                if (rank[a] == t)
+                    tf[t][r] = v;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (rank[a] == D + c)
+                    nf[c][r] = v;
+        }
+    }
+
+    // local coordinates and the spacing h (Eq. DefH and its two-dimensional form)
+    T umin[D], umax[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        umin[t] = (T)INFINITY;
+        umax[t] = -(T)INFINITY;
+    }
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+        T u[D], z[NC];
+        local_coords<T, NA, D>(spts[list[k * kWave + lane]], qp, tf, nf, u, z);
+#pragma unroll
+        for (int t = 0; t < D; ++t) {
+            umin[t] = min(umin[t], u[t]);
+            umax[t] = max(umax[t], u[t]);
+        }
+    }
+    T range = umax[0] - umin[0];
+#pragma unroll
+    for (int t = 1; t < D; ++t)
+        range = min(range, umax[t] - umin[t]);
+    const T hT = (T)0.25 * range;
+    double h = P.use_h ? P.h_override : (double)hT;
+    bool degenerate = !(h > 0.0) || !isfinite(h);
+    const T ih = degenerate ? (T)0 : (T)(1.0 / h);
+
+    // Gram matrix of the design over {p_i} u N(i) and right-hand sides of the surface fits,
+    // weighted: V^T W V and V^T W z with W = diag(1, w_nbr, ..., w_nbr)
+    const double wn = P.w_nbr;
+    double Gm[NG], rz[NC][M];
+#pragma unroll
+    for (int t = 0; t < NG; ++t)
+        Gm[t] = 0.0;
+    Gm[0] = 1.0; // centre row (1, 0, ..., 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int t = 0; t < M; ++t)
+            rz[c][t] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+        T u[D], z[NC];
+        local_coords<T, NA, D>(spts[list[k * kWave + lane]], qp, tf, nf, u, z);
+        double mv[M], wm[M];
+        monomials<T, D>(u, ih, mv);
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+            wm[i] = wn * mv[i];
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = i; j < M; ++j)
+                Gm[symM<M>(i, j)] = fma(wm[i], mv[j], Gm[symM<M>(i, j)]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double zc = (double)z[c];
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+                rz[c][i] = fma(wm[i], zc, rz[c][i]);
+        }
+    }
+    double inv_d[M];
+    if (!degenerate)
+        degenerate = !chol_packed<M>(Gm, inv_d);
+
+    double y[M], tau = 0.0;
+#pragma unroll
+    for (int t = 0; t < M; ++t)
+        y[t] = 0.0;
+    if (!degenerate) {
+        const double ihd = 1.0 / h, ih2 = ihd * ihd;
+        double scale[M];
+        scale[0] = 1.0;
+#pragma unroll
+        for (int t = 1; t <= D; ++t)
+            scale[t] = ihd;
+#pragma unroll
+        for (int t = D + 1; t < M; ++t)
+            scale[t] = ih2;
+        // fitted graph of every normal coordinate (Eq. poly), unscaled coefficients
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            chol_packed_solve<M>(Gm, inv_d, rz[c]);
+        if (sizeof(T) == 8) {
+            // one refinement step of the surface fits, residual V^T W (z - V a) formed from V
+            double res[NC][M];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                for (int t = 0; t < M; ++t)
+                    res[c][t] = 0.0;
+                res[c][0] = -rz[c][0]; // centre row e1 with z = 0
+            }
+#pragma unroll 4
+            for (int k = 0; k < K; ++k) {
+                T u[D], z[NC];
+                local_coords<T, NA, D>(spts[list[k * kWave + lane]], qp, tf, nf, u, z);
+                double mv[M];
+                monomials<T, D>(u, ih, mv);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    double e = (double)z[c];
+#pragma unroll
+                    for (int t = 0; t < M; ++t)
+                        e = fma(-mv[t], rz[c][t], e);
+                    e *= wn;
+#pragma unroll
+                    for (int t = 0; t < M; ++t)
+                        res[c][t] = fma(mv[t], e, res[c][t]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                chol_packed_solve<M>(Gm, inv_d, res[c]);
+#pragma unroll
+                for (int t = 0; t < M; ++t)
+                    rz[c][t] += res[c][t];
+            }
+        }
+        double ell[M];
+        bool ok = true;
+        if constexpr (D == 2) {
+            // inverse metric (Eq. metric) and the first-order coefficients of Eq. eqn3
+            double g11 = 1.0, g12 = 0.0, g22 = 1.0;
+            double zx[NC], zy[NC], h11[NC], h12[NC], h22[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                zx[c] = rz[c][1] * scale[1];
+                zy[c] = rz[c][2] * scale[2];
+                h11[c] = 2.0 * rz[c][3] * scale[3];
+                h12[c] = rz[c][4] * scale[4];
+                h22[c] = 2.0 * rz[c][5] * scale[5];
+                g11 = fma(zx[c], zx[c], g11);
+                g12 = fma(zx[c], zy[c], g12);
+                g22 = fma(zy[c], zy[c], g22);
+            }
+            const double det = g11 * g22 - g12 * g12;
+            const double idet = 1.0 / det;
+            const double G11 = g22 * idet, G12 = -g12 * idet, G22 = g11 * idet;
+            double q1 = 0.0, q2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double tr = G11 * h11[c] + 2.0 * G12 * h12[c] + G22 * h22[c];
+                q1 = fma(tr, G11 * zx[c] + G12 * zy[c], q1);
+                q2 = fma(tr, G12 * zx[c] + G22 * zy[c], q2);
+            }
+            tau = (P.variant == 0) ? 2.0 * (G11 + G22) * ih2 : 0.0;
+            ell[0] = tau; ell[1] = -q1; ell[2] = -q2;
+            ell[3] = 2.0 * G11; ell[4] = 2.0 * G12; ell[5] = 2.0 * G22;
+            ok = det > 0.0;
+        } else if (P.variant == 2) {
+            // divergence form (Eq. divergence): s(x) = sqrt(1 + sum_c y_c'(x)^2) of the fitted
+            // curve, a+- = 1 / (h^2 s(0) s(+-h/2)), L_i U = a+ U(h) + a- U(-h) - (a+ + a-) U_i
+            double s0 = 1.0, sp = 1.0, sm = 1.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double a1 = rz[c][1] * scale[1], a2 = rz[c][2] * scale[2];
+                const double dp = a1 + a2 * h, dm = a1 - a2 * h; // y' at +-h/2
+                s0 = fma(a1, a1, s0);
+                sp = fma(dp, dp, sp);
+                sm = fma(dm, dm, sm);
+            }
+            const double r0 = sqrt(s0);
+            const double ap = ih2 / (r0 * sqrt(sp)), am = ih2 / (r0 * sqrt(sm));
+            tau = ap + am;
+            ell[0] = tau; ell[1] = (ap - am) * h; ell[2] = tau * h * h;
+        } else {
+            // Eq. LB1: G = 1 / (1 + |y'|^2), q = sum_c (G y_c'') (G y_c')
+            double g = 1.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                g = fma(rz[c][1] * scale[1], rz[c][1] * scale[1], g);
+            const double G = 1.0 / g;
+            double qs = 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                qs = fma(G * 2.0 * rz[c][2] * scale[2], G * rz[c][1] * scale[1], qs);
+            tau = (P.variant == 0) ? 2.0 * G * ih2 : 0.0;
+            ell[0] = tau; ell[1] = -qs; ell[2] = 2.0 * G;
+        }
+        double dl[M];
+#pragma unroll
+        for (int t = 0; t < M; ++t) {
+            dl[t] = ell[t] * scale[t];
+            y[t] = dl[t];
+        }
+        chol_packed_solve<M>(Gm, inv_d, y);
+        degenerate = !ok || !isfinite(tau) || !isfinite(y[0]);
+        if (sizeof(T) == 8 && !degenerate) {
+            // one refinement step on V^T W V y = D ell with the residual formed from V itself
+            double res[M];
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                res[t] = dl[t];
+            res[0] -= y[0]; // centre row e1: (V y)_0 = y0
+#pragma unroll 4
+            for (int k = 0; k < K; ++k) {
+                T u[D], z[NC];
+                local_coords<T, NA, D>(spts[list[k * kWave + lane]], qp, tf, nf, u, z);
+                double mv[M];
+                monomials<T, D>(u, ih, mv);
+                double w = 0.0;
+#pragma unroll
+                for (int t = 0; t < M; ++t)
+                    w = fma(mv[t], y[t], w);
+                w *= wn;
+#pragma unroll
+                for (int t = 0; t < M; ++t)
+                    res[t] = fma(-w, mv[t], res[t]);
+            }
+            chol_packed_solve<M>(Gm, inv_d, res);
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                y[t] += res[t];
+        }
+    }
+
+    // weights w = W V y (centre: y0 - tau) into the sliced ELL, slot 0 = centre
+    const int64_t ld = P.ld;
+    P.ell_col[q] = q;
+    val[q] = degenerate ? (T)0 : (T)(y[0] - tau);
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+        const int pos = list[k * kWave + lane];
+        double w = 0.0;
+        if (!degenerate) {
+            T u[D], z[NC];
+            local_coords<T, NA, D>(spts[pos], qp, tf, nf, u, z);
+            double mv[M];
+            monomials<T, D>(u, ih, mv);
+#pragma unroll
+            for (int t = 0; t < M; ++t)
+                w = fma(mv[t], y[t], w);
+            w *= wn;
+        }
+        P.ell_col[(int64_t)(k + 1) * ld + q] = pos;
+        val[(int64_t)(k + 1) * ld + q] = (T)w;
+    }
+    bool close_pair = false; // tangent eigenvalues within 1e-3 (in-plane frame ill-defined)
+    if constexpr (D == 2)
+        close_pair = (lam_t[0] - lam_t[1]) < 1e-3 * lam_t[0];
+    if (P.row_h)
+        P.row_h[q] = h;
+    if (P.row_flags)
+        P.row_flags[q] = (uint8_t)((degenerate ? 1 : 0) | (slow_row ? 2 : 0) | (close_pair ? 4 : 0));
+    const unsigned long long nd = __popcll(__ballot(degenerate));
+    const unsigned long long ns = __popcll(__ballot(slow_row));
+    if (lane == __ffsll((long long)__ballot(true)) - 1) {
+        if (nd)
+            atomicAdd(&P.counters[0], nd);
+        if (ns)
+            atomicAdd(&P.counters[1], ns);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------------------------
-template <typename T, int NA>
+template <typename T, int NA, int D>
 __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t group, char *lds)
 {
-    constexpr int NC = NA - 2; // normal coordinates
     const int lane = lane_id();
     const int K = P.K;
     char *lds_rng = lds + kLdsList + K * kWave * 4;
@@ -659,322 +1056,13 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
 #pragma unroll 4
     for (int k = 0; k < K; ++k)
         list[k * kWave + lane] = P.iperm[list[k * kWave + lane]];
-    T *val = (T *)P.ell_val;
-    double qd[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-        qd[a] = (double)qp.v[a];
-
-    // covariance about the barycentre of N(i) (p_i excluded), FP64 from exact differences
-    double s1[NA], s2[NA][NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        s1[a] = 0.0;
-#pragma unroll
-        for (int c = 0; c < NA; ++c)
-            s2[a][c] = 0.0;
-    }
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-        const Pt<T> pj = spts[list[k * kWave + lane]];
-        double dv[NA];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            dv[a] = (double)pj.v[a] - qd[a];
-            s1[a] += dv[a];
-        }
-#pragma unroll
-        for (int a = 0; a < NA; ++a)
-#pragma unroll
-            for (int c = a; c < NA; ++c)
-                s2[a][c] = fma(dv[a], dv[c], s2[a][c]);
-    }
-    const double invK = 1.0 / (double)K;
-    double A[NA][NA], W[NA][NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-        for (int c = a; c < NA; ++c) {
-            A[a][c] = s2[a][c] - s1[a] * s1[c] * invK;
-            A[c][a] = A[a][c];
-        }
-    jacobi_eig<NA>(A, W);
-    double lam[NA];
-    int rank[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-        lam[a] = A[a][a];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-        rank[a] = 0;
-#pragma unroll
-        for (int c = 0; c < NA; ++c)
-            rank[a] += (c != a) && (lam[c] > lam[a] || (lam[c] == lam[a] && c < a));
-    }
-    T tf[2][NA], nf[NC][NA];
-    double lam_t[2] = {0.0, 0.0};
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-            if (rank[a] == t)
-                lam_t[t] = lam[a];
-#pragma unroll
-        for (int r = 0; r < NA; ++r) {
-            const T v = (T)W[r][a];
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-                if (rank[a] == t)
-                    tf[t][r] = v;
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (rank[a] == 2 + c)
-                    nf[c][r] = v;
-        }
-    }
-
-    // local coordinates and the spacing h (Eq. DefH)
-    T umin0 = (T)INFINITY, umax0 = -(T)INFINITY, umin1 = (T)INFINITY, umax1 = -(T)INFINITY;
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-        const Pt<T> pj = spts[list[k * kWave + lane]];
-        T u0 = 0, u1 = 0;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const T d = pj.v[a] - qp.v[a];
-            u0 += tf[0][a] * d;
-            u1 += tf[1][a] * d;
-        }
-        umin0 = min(umin0, u0); umax0 = max(umax0, u0);
-        umin1 = min(umin1, u1); umax1 = max(umax1, u1);
-    }
-    const T hT = (T)0.25 * min(umax0 - umin0, umax1 - umin1);
-    double h = P.use_h ? P.h_override : (double)hT;
-    bool degenerate = !(h > 0.0) || !isfinite(h);
-    const T ih = degenerate ? (T)0 : (T)(1.0 / h);
-
-    // Gram matrix of the design over {p_i} u N(i) and right-hand sides of the surface fits,
-    // weighted: V^T W V and V^T W z with W = diag(1, w_nbr, ..., w_nbr)
-    const double wn = P.w_nbr;
-    double Gm[21], rz[NC][6];
-#pragma unroll
-    for (int t = 0; t < 21; ++t)
-        Gm[t] = 0.0;
-    Gm[0] = 1.0; // centre row (1, 0, 0, 0, 0, 0)
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int t = 0; t < 6; ++t)
-            rz[c][t] = 0.0;
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-        const Pt<T> pj = spts[list[k * kWave + lane]];
-        T u0 = 0, u1 = 0, z[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            z[c] = 0;
-#pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            const T d = pj.v[a] - qp.v[a];
-            u0 += tf[0][a] * d;
-            u1 += tf[1][a] * d;
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                z[c] += nf[c][a] * d;
-        }
-        double mv[6], wm[6];
-        monomials<T>(u0 * ih, u1 * ih, mv);
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-            wm[i] = wn * mv[i];
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-#pragma unroll
-            for (int j = i; j < 6; ++j)
-                Gm[sym6(i, j)] = fma(wm[i], mv[j], Gm[sym6(i, j)]);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double zc = (double)z[c];
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-                rz[c][i] = fma(wm[i], zc, rz[c][i]);
-        }
-    }
-    double inv_d[6];
-    if (!degenerate)
-        degenerate = !chol6(Gm, inv_d);
-
-    double y[6] = {0, 0, 0, 0, 0, 0}, tau = 0.0;
-    if (!degenerate) {
-        const double ihd = 1.0 / h, ih2 = ihd * ihd;
-        const double scale[6] = {1.0, ihd, ihd, ih2, ih2, ih2};
-        // fitted graph of every normal coordinate (Eq. poly), unscaled coefficients
-        double g11 = 1.0, g12 = 0.0, g22 = 1.0;
-        double zx[NC], zy[NC], h11[NC], h12[NC], h22[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            chol6_solve(Gm, inv_d, rz[c]);
-        if (sizeof(T) == 8) {
-            // one refinement step of the surface fits, residual V^T (z - V a) formed from V
-            double res[NC][6];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-#pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    res[c][t] = 0.0;
-                res[c][0] = -rz[c][0]; // centre row e1 with z = 0
-            }
-#pragma unroll 4
-            for (int k = 0; k < K; ++k) {
-                const Pt<T> pj = spts[list[k * kWave + lane]];
-                T u0 = 0, u1 = 0, z[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    z[c] = 0;
-#pragma unroll
-                for (int a = 0; a < NA; ++a) {
-                    const T d = pj.v[a] - qp.v[a];
-                    u0 += tf[0][a] * d;
-                    u1 += tf[1][a] * d;
-#pragma unroll
-                    for (int c = 0; c < NC; ++c)
-                        z[c] += nf[c][a] * d;
-                }
-                double mv[6];
-                monomials<T>(u0 * ih, u1 * ih, mv);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    double e = (double)z[c];
-#pragma unroll
-                    for (int t = 0; t < 6; ++t)
-                        e = fma(-mv[t], rz[c][t], e);
-                    e *= wn;
-#pragma unroll
-                    for (int t = 0; t < 6; ++t)
-                        res[c][t] = fma(mv[t], e, res[c][t]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                chol6_solve(Gm, inv_d, res[c]);
-#pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    rz[c][t] += res[c][t];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            zx[c] = rz[c][1] * scale[1];
-            zy[c] = rz[c][2] * scale[2];
-            h11[c] = 2.0 * rz[c][3] * scale[3];
-            h12[c] = rz[c][4] * scale[4];
-            h22[c] = 2.0 * rz[c][5] * scale[5];
-            g11 = fma(zx[c], zx[c], g11);
-            g12 = fma(zx[c], zy[c], g12);
-            g22 = fma(zy[c], zy[c], g22);
-        }
-        // inverse metric (Eq. metric) and the first-order coefficients of Eq. eqn3
-        const double det = g11 * g22 - g12 * g12;
-        const double idet = 1.0 / det;
-        const double G11 = g22 * idet, G12 = -g12 * idet, G22 = g11 * idet;
-        double q1 = 0.0, q2 = 0.0;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double tr = G11 * h11[c] + 2.0 * G12 * h12[c] + G22 * h22[c];
-            q1 = fma(tr, G11 * zx[c] + G12 * zy[c], q1);
-            q2 = fma(tr, G12 * zx[c] + G22 * zy[c], q2);
-        }
-        tau = (P.variant == 0) ? 2.0 * (G11 + G22) * ih2 : 0.0;
-        const double ell[6] = {tau, -q1, -q2, 2.0 * G11, 2.0 * G12, 2.0 * G22};
-        double dl[6];
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-            dl[t] = ell[t] * scale[t];
-            y[t] = dl[t];
-        }
-        chol6_solve(Gm, inv_d, y);
-        degenerate = !(det > 0.0) || !isfinite(tau) || !isfinite(y[0]);
-        if (sizeof(T) == 8 && !degenerate) {
-            // one refinement step on V^T w = D ell with the residual formed from V itself
-            double res[6];
-#pragma unroll
-            for (int t = 0; t < 6; ++t)
-                res[t] = dl[t];
-            res[0] -= y[0]; // centre row e1: (V y)_0 = y0
-#pragma unroll 4
-            for (int k = 0; k < K; ++k) {
-                const Pt<T> pj = spts[list[k * kWave + lane]];
-                T u0 = 0, u1 = 0;
-#pragma unroll
-                for (int a = 0; a < NA; ++a) {
-                    const T d = pj.v[a] - qp.v[a];
-                    u0 += tf[0][a] * d;
-                    u1 += tf[1][a] * d;
-                }
-                double mv[6];
-                monomials<T>(u0 * ih, u1 * ih, mv);
-                double w = 0.0;
-#pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    w = fma(mv[t], y[t], w);
-                w *= wn;
-#pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    res[t] = fma(-w, mv[t], res[t]);
-            }
-            chol6_solve(Gm, inv_d, res);
-#pragma unroll
-            for (int t = 0; t < 6; ++t)
-                y[t] += res[t];
-        }
-    }
-
-    // weights w = V y (centre: y0 - tau) into the sliced ELL, slot 0 = centre
-    const int64_t ld = P.ld;
-    P.ell_col[q] = q;
-    val[q] = degenerate ? (T)0 : (T)(y[0] - tau);
-#pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-        const int pos = list[k * kWave + lane];
-        double w = 0.0;
-        if (!degenerate) {
-            const Pt<T> pj = spts[pos];
-            T u0 = 0, u1 = 0;
-#pragma unroll
-            for (int a = 0; a < NA; ++a) {
-                const T d = pj.v[a] - qp.v[a];
-                u0 += tf[0][a] * d;
-                u1 += tf[1][a] * d;
-            }
-            double mv[6];
-            monomials<T>(u0 * ih, u1 * ih, mv);
-#pragma unroll
-            for (int t = 0; t < 6; ++t)
-                w = fma(mv[t], y[t], w);
-            w *= wn;
-        }
-        P.ell_col[(int64_t)(k + 1) * ld + q] = pos;
-        val[(int64_t)(k + 1) * ld + q] = (T)w;
-    }
-    if (P.row_h)
-        P.row_h[q] = h;
-    if (P.row_flags)
-        P.row_flags[q] = (uint8_t)((degenerate ? 1 : 0) | (slow_row ? 2 : 0) |
-                                   ((lam_t[0] - lam_t[1]) < 1e-3 * lam_t[0] ? 4 : 0));
-    const unsigned long long nd = __popcll(__ballot(degenerate));
-    const unsigned long long ns = __popcll(__ballot(slow_row));
-    if (lane == __ffsll((long long)__ballot(true)) - 1) {
-        if (nd)
-            atomicAdd(&P.counters[0], nd);
-        if (ns)
-            atomicAdd(&P.counters[1], ns);
-    }
+    fit_row<T, NA, D>(P, spts, list, lane, q, qp, slow_row);
 }
 
 // Grid-mapped launch: one workgroup per group, XCD-aware remap (workgroups are dispatched to the
 // eight XCDs round-robin, so workgroup b runs on XCD b % 8; consecutive groups, which are
 // neighbours in space, go to the same XCD and share its L2).
-template <typename T, int NA>
+template <typename T, int NA, int D>
 __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -982,14 +1070,14 @@ __global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
     const int64_t group = (b & 7) * P.groups_per_xcd + (b >> 3);
     if (group >= P.n_groups)
         return;
-    assemble_group<T, NA>(P, group, lds);
+    assemble_group<T, NA, D>(P, group, lds);
 }
 
 // Persistent launch: as many workgroups as fit on the device at once; each pops groups from the
 // queue of its XCD (queue x owns groups [x * groups_per_xcd, (x + 1) * groups_per_xcd)) and,
 // when that queue is empty, steals from the others in turn. Every workgroup exits once all eight
 // queues are exhausted. The queue counters must be zero at launch.
-template <typename T, int NA>
+template <typename T, int NA, int D>
 __global__ __launch_bounds__(64) void assemble_persistent_kernel(AsmParams P)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -1007,7 +1095,7 @@ __global__ __launch_bounds__(64) void assemble_persistent_kernel(AsmParams P)
             t = (unsigned int)uniform((int)t);
             if ((int64_t)t >= len)
                 break;
-            assemble_group<T, NA>(P, base + t, lds);
+            assemble_group<T, NA, D>(P, base + t, lds);
             __syncthreads();
         }
     }

@@ -189,7 +189,7 @@ struct PlanArgs {
     int32_t n_clouds;
     int32_t n_amb;
     int32_t K;
-    int32_t pad;
+    int32_t d;             // manifold dimension (1: curves, 2: surfaces)
     double alpha;          // cell edge / estimated K-th neighbour distance
     double mu;             // initial search radius / estimated K-th neighbour distance
     Proj proj;
@@ -204,7 +204,8 @@ __device__ __forceinline__ double ord_decode(unsigned long long u)
 }
 
 // Cell edge from the estimated K-th neighbour distance of a surface sample (the area of a closed
-// surface is taken as about half the surface of its projected bounding box), coarsened until the
+// surface is taken as about half the surface of its projected bounding box) or of a curve sample
+// (from an estimated length), coarsened until the
 // power-of-two grid fits the cloud's cell budget; Morton part tables interleave the bits of the
 // three cell coordinates (axes with fewer bits drop out of the higher levels).
 __global__ __launch_bounds__(256) void plan_kernel(PlanArgs a)
@@ -232,8 +233,14 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanArgs a)
         double Ef[3];
         for (int k = 0; k < 3; ++k)
             Ef[k] = fmax(Eb[k], emax * 1e-3);
-        const double area = 0.55 * 2.0 * (Ef[0] * Ef[1] + Ef[1] * Ef[2] + Ef[0] * Ef[2]);
-        double dk = sqrt((double)a.K * area / (M_PI * (double)n));
+        double dk;
+        if (a.d == 2) {
+            const double area = 0.55 * 2.0 * (Ef[0] * Ef[1] + Ef[1] * Ef[2] + Ef[0] * Ef[2]);
+            dk = sqrt((double)a.K * area / (M_PI * (double)n));
+        } else { // a closed curve is taken as about 1.6 times the sum of the box edges long
+            const double len = 1.6 * (Eb[0] + Eb[1] + Eb[2]);
+            dk = (double)a.K * len / (2.0 * (double)n);
+        }
         if (!(dk > 0.0 && dk < 1e300)) // extent below the double range, or no finite point
             dk = (emax > 1e-300 && emax < 1e300) ? emax : 1.0;
         double cell = a.alpha * dk;

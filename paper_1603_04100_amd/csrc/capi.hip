@@ -188,14 +188,14 @@ void release(mvgd_matrix *L)
     delete L;
 }
 
-// The fixed binning projection (rows orthonormal): identity for n = 3, a generic 3x4 matrix for
-// n = 4 (see Proj in common.hpp).
+// The fixed binning projection (rows orthonormal): identity for n = 2 and 3, a generic 3x4
+// matrix for n = 4 (see Proj in common.hpp).
 Proj binning_projection(int n_amb)
 {
     Proj pr;
     memset(&pr, 0, sizeof pr);
-    if (n_amb == 3) {
-        for (int a = 0; a < 3; ++a)
+    if (n_amb <= 3) { // identity (n = 2: the third projected coordinate is 0)
+        for (int a = 0; a < n_amb; ++a)
             pr.W[a][a] = 1.0;
         return pr;
     }
@@ -266,7 +266,7 @@ void *staging(size_t bytes)
 }
 
 // Occupancy of the persistent assembly kernel (blocks per CU) per (precision, n, K), queried once.
-std::atomic<int> g_occupancy[2][2][kMaxK + 1];
+std::atomic<int> g_occupancy[2][3][2][kMaxK + 1]; // [double][n - 2][d - 1][K]
 std::atomic<int> g_n_cu{0};
 
 template <typename T>
@@ -417,7 +417,9 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     const Proj proj = binning_projection(n_amb);
     {
         const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(512, (max_n + 2047) / 2048));
-        if (n_amb == 3)
+        if (n_amb == 2)
+            bbox_kernel<T, 2><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
+        else if (n_amb == 3)
             bbox_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
         else
             bbox_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
@@ -430,6 +432,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         pa.n_clouds = n_clouds;
         pa.n_amb = n_amb;
         pa.K = K;
+        pa.d = p.d_manifold;
         pa.alpha = tunable(p.cell_alpha, kDefaultCellAlpha);
         pa.mu = tunable(p.radius_mu, kDefaultRadiusMu);
         pa.proj = proj;
@@ -440,7 +443,10 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     if (hipMemsetAsync(d_counts, 0, sizeof(uint32_t) * cell_total, stream) != hipSuccess)
         return fail(MVGD_EDEVICE, "clearing the cell counts failed");
     const int bx = (int)std::min<int64_t>(2048, (max_n + 255) / 256);
-    if (n_amb == 3)
+    if (n_amb == 2)
+        key_kernel<T, 2><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
+                                                                  d_counts, d_keys, d_slots);
+    else if (n_amb == 3)
         key_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
                                                                   d_counts, d_keys, d_slots);
     else
@@ -495,7 +501,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.K = K;
     ap.n_groups = group_total;
     ap.groups_per_xcd = (group_total + 7) / 8;
-    ap.variant = (p.flags & MVGD_FLAG_LS) ? 1 : 0;
+    ap.variant = (p.flags & MVGD_FLAG_LS) ? 1 : (p.flags & MVGD_FLAG_DIVERGENCE) ? 2 : 0;
     ap.use_h = (p.flags & MVGD_FLAG_H_OVERRIDE) ? 1 : 0;
     ap.h_override = p.h_override;
     ap.w_nbr = (p.flags & MVGD_FLAG_MLS) ? 1.0 / (double)K : 1.0;
@@ -509,11 +515,15 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     const size_t lds = (size_t)lds_bytes(K, (int)sizeof(Pt<T>));
     const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
     unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
+    const int d = p.d_manifold;
     if (persistent) {
-        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb == 4][K];
+        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb - 2][d - 1][K];
         int per_cu = occ.load(), n_cu = g_n_cu.load();
         if (per_cu <= 0 || n_cu <= 0) {
-            auto kern = n_amb == 3 ? assemble_persistent_kernel<T, 3> : assemble_persistent_kernel<T, 4>;
+            const void *kern = n_amb == 4 ? (const void *)assemble_persistent_kernel<T, 4, 2>
+                             : d == 2 ? (const void *)assemble_persistent_kernel<T, 3, 2>
+                             : n_amb == 3 ? (const void *)assemble_persistent_kernel<T, 3, 1>
+                                          : (const void *)assemble_persistent_kernel<T, 2, 1>;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess ||
                 hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
                 return fail(MVGD_EDEVICE, "occupancy query failed");
@@ -527,17 +537,22 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     }
     if (L->ev[1])
         (void)hipEventRecord(L->ev[1], stream);
-    if (persistent) {
-        if (n_amb == 3)
-            assemble_persistent_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
-        else
-            assemble_persistent_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
-    } else {
-        if (n_amb == 3)
-            assemble_kernel<T, 3><<<nblk, kWave, lds, stream>>>(ap);
-        else
-            assemble_kernel<T, 4><<<nblk, kWave, lds, stream>>>(ap);
-    }
+#define MVGD_LAUNCH(NA_, D_)                                                                      \
+    do {                                                                                          \
+        if (persistent)                                                                           \
+            assemble_persistent_kernel<T, NA_, D_><<<nblk, kWave, lds, stream>>>(ap);             \
+        else                                                                                      \
+            assemble_kernel<T, NA_, D_><<<nblk, kWave, lds, stream>>>(ap);                        \
+    } while (0)
+    if (d == 2 && n_amb == 3)
+        MVGD_LAUNCH(3, 2);
+    else if (d == 2)
+        MVGD_LAUNCH(4, 2);
+    else if (n_amb == 3)
+        MVGD_LAUNCH(3, 1);
+    else
+        MVGD_LAUNCH(2, 1);
+#undef MVGD_LAUNCH
     if (mvgd_status st = check_launch("assemble"); st != MVGD_OK)
         return st;
     if (L->ev[2])
@@ -556,19 +571,23 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
     *out = nullptr;
     if (!points || !p)
         return fail(MVGD_EINVAL, "points or params is NULL");
-    if (p->d_manifold == 1)
-        return fail(MVGD_EUNSUPPORTED, "curves (d = 1) are not implemented on the GPU path");
-    if (p->d_manifold != 2)
-        return fail(MVGD_EINVAL, "d_manifold must be 2");
-    if (p->n_ambient != 3 && p->n_ambient != 4)
-        return fail(MVGD_EINVAL, "n_ambient must be 3 or 4 (got %d)", p->n_ambient);
-    if (p->k < 5 || p->k > kMaxK)
-        return fail(MVGD_EINVAL, "k must be in [5, %d] (got %d)", kMaxK, p->k);
+    if (p->d_manifold != 1 && p->d_manifold != 2)
+        return fail(MVGD_EINVAL, "d_manifold must be 1 or 2 (got %d)", p->d_manifold);
+    if (p->d_manifold == 2 && p->n_ambient != 3 && p->n_ambient != 4)
+        return fail(MVGD_EINVAL, "surfaces need n_ambient 3 or 4 (got %d)", p->n_ambient);
+    if (p->d_manifold == 1 && p->n_ambient != 2 && p->n_ambient != 3)
+        return fail(MVGD_EINVAL, "curves need n_ambient 2 or 3 (got %d)", p->n_ambient);
+    const int k_min = p->d_manifold == 2 ? 5 : 2; // at least as many points as monomials
+    if (p->k < k_min || p->k > kMaxK)
+        return fail(MVGD_EINVAL, "k must be in [%d, %d] (got %d)", k_min, kMaxK, p->k);
     if (p->precision != MVGD_FP64 && p->precision != MVGD_FP32_MIXED)
         return fail(MVGD_EINVAL, "unknown precision %d", p->precision);
     if (p->flags & ~(uint32_t)(MVGD_FLAG_LS | MVGD_FLAG_H_OVERRIDE | MVGD_FLAG_KEEP_DIAG |
-                             MVGD_FLAG_TIME | MVGD_FLAG_MLS))
+                             MVGD_FLAG_TIME | MVGD_FLAG_MLS | MVGD_FLAG_DIVERGENCE))
         return fail(MVGD_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if ((p->flags & MVGD_FLAG_DIVERGENCE) &&
+        (p->d_manifold != 1 || (p->flags & MVGD_FLAG_LS)))
+        return fail(MVGD_EINVAL, "the divergence form is for curves (d = 1) and excludes LS");
     if ((p->flags & MVGD_FLAG_H_OVERRIDE) && !(p->h_override > 0.0 && std::isfinite(p->h_override)))
         return fail(MVGD_EINVAL, "h_override must be positive and finite");
     if (p->launch < MVGD_LAUNCH_DEFAULT || p->launch > MVGD_LAUNCH_PERSISTENT)

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libmvgd.so")
 MVGD_OK, MVGD_EINVAL, MVGD_ENOMEM, MVGD_EDEVICE, MVGD_EUNSUPPORTED = 0, -1, -2, -3, -4
 MVGD_FP64, MVGD_FP32_MIXED = 0, 1
 MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 4, 8
-MVGD_FLAG_MLS = 16
+MVGD_FLAG_MLS, MVGD_FLAG_DIVERGENCE = 16, 32
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
            "mvgd_timing", "mvgd_row_stats", "mvgd_pool_trim", "mvgd_status_str",

@@ -63,7 +63,7 @@ def _call(mv, params, n_total=1000, offsets=None, n_clouds=1, points=0x1000, out
 
 @pytest.mark.parametrize("field,value,status", [
     ("k", 4, -1), ("k", 64, -1), ("n_ambient", 2, -1), ("n_ambient", 5, -1),
-    ("d_manifold", 3, -1), ("d_manifold", 1, -4), ("precision", 7, -1), ("flags", 1 << 9, -1),
+    ("d_manifold", 3, -1), ("d_manifold", 0, -1), ("precision", 7, -1), ("flags", 1 << 9, -1),
 ])
 def test_invalid_parameters_rejected_on_host(mv, field, value, status):
     p = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, 0, 0.0)
@@ -71,6 +71,18 @@ def test_invalid_parameters_rejected_on_host(mv, field, value, status):
     st, h = _call(mv, p)
     assert st == status and h is None
     assert mv._lib.mvgd_last_error()
+
+
+@pytest.mark.parametrize("n_amb,d,k,flags", [
+    (4, 1, 6, 0),      # curves live in R^2 or R^3
+    (3, 1, 1, 0),      # K >= 2 for the three monomials of a curve
+    (3, 2, 20, 32),    # the divergence form is for curves
+    (2, 1, 6, 32 | 1), # and excludes the LS variant
+])
+def test_curve_parameters_rejected_on_host(mv, n_amb, d, k, flags):
+    p = mv.mvgd_params(n_amb, d, k, mv.MVGD_FP64, flags, 0.0)
+    st, h = _call(mv, p)
+    assert st == -1 and h is None
 
 
 def test_invalid_shapes_rejected_on_host(mv):

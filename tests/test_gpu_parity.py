@@ -14,6 +14,9 @@ Bars (the targets of the build):
 * Apply: y = L x against the exported CSR times x in FP64 (accumulation in double on the GPU).
 Every case prints its L.f error against the FP64 oracle.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -46,17 +49,22 @@ def _oracle_points(pts, precision):
     return pts.astype(np.float32).astype(np.float64) if precision == "fp32" else pts
 
 
-def _kappa(pts, rows, cols, dg, w_nbr=1.0):
+def _kappa(pts, rows, cols, dg, w_nbr=1.0, d=2):
     """2-norm condition number of each row's (weighted) design W^1/2 V (centre row, then N(i)),
     from the oracle's frame and spacing."""
     n = pts.shape[1]
     i = np.asarray(rows)
     nb = cols[cols != i[:, None]].reshape(len(i), -1)
-    F = dg[:, 6:22].reshape(-1, 4, 4)[:, :2, :n]
+    F = dg[:, 6:22].reshape(-1, 4, 4)[:, :d, :n]
     u = np.einsum("rkn,rtn->rkt", pts[nb] - pts[i][:, None, :], F) / dg[:, 0][:, None, None]
-    x, y = u[..., 0], u[..., 1]
-    V = np.stack([np.ones_like(x), x, y, x * x, x * y, y * y], -1) * np.sqrt(w_nbr)
-    V = np.concatenate([np.eye(6)[None, :1, :].repeat(len(i), 0), V], 1)
+    if d == 2:
+        x, y = u[..., 0], u[..., 1]
+        V = np.stack([np.ones_like(x), x, y, x * x, x * y, y * y], -1) * np.sqrt(w_nbr)
+    else:
+        x = u[..., 0]
+        V = np.stack([np.ones_like(x), x, x * x], -1) * np.sqrt(w_nbr)
+    m = V.shape[-1]
+    V = np.concatenate([np.eye(m)[None, :1, :].repeat(len(i), 0), V], 1)
     s = np.linalg.svd(V, compute_uv=False)
     return s[:, 0] / s[:, -1]
 
@@ -95,10 +103,12 @@ def _full_case(mv, cl, precision, **kw):
     L, P, rp, col, val, info = _gpu_csr(mv, pts, k, precision, **kw)
     opts = _oracle_points(pts, precision)
     flags = kw.get("flags", 0)
+    d = kw.get("d_manifold", 2)
     w_nbr = 1.0 / k if flags & mv.MVGD_FLAG_MLS else 1.0
-    o_cols, o_vals, dg = oracle.rows(opts, k, diag=True, weight_nbr=w_nbr,
-                                     variant="ls" if flags & mv.MVGD_FLAG_LS else "mvgd")
-    kap = _kappa(opts, np.arange(n), o_cols, dg, w_nbr)
+    variant = ("ls" if flags & mv.MVGD_FLAG_LS else
+               "div" if flags & mv.MVGD_FLAG_DIVERGENCE else "mvgd")
+    o_cols, o_vals, dg = oracle.rows(opts, k, diag=True, weight_nbr=w_nbr, variant=variant, d=d)
+    kap = _kappa(opts, np.arange(n), o_cols, dg, w_nbr, d)
     rel = _compare_rows(col.reshape(n, k + 1), val.reshape(n, k + 1), o_cols, o_vals,
                         _row_tol(precision, dg, kap))
     assert (rp == np.arange(n + 1) * (k + 1)).all()
@@ -258,6 +268,60 @@ def test_row_stats_paper_claim_on_the_gpu(mv):
         f"{k}: M-rows {v['n_m_rows']}/{n}, mean ratio {v['mean_ratio']:.4f}" for k, v in res.items()))
 
 
+# ----------------------------------------------------------------------------------------------
+# curves (d = 1): centred and divergence forms, plain LS, MLS weights
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["circle-mvgd", "circle-div", "helix-mvgd", "helix-div",
+                                  "helix-ls-mls", "circle-uniform-mvgd"])
+def test_curves(mv, precision, case):
+    if case.startswith("circle"):
+        cl = clouds.circle(4000, 61, 6, sampling="uniform" if "uniform" in case else "random")
+    else:
+        cl = clouds.helix(5000, 62, 8)
+    flags = {"mvgd": 0, "div": mv.MVGD_FLAG_DIVERGENCE,
+             "mls": mv.MVGD_FLAG_LS | mv.MVGD_FLAG_MLS}[case.split("-")[-1]]
+    L, *_ = _full_case(mv, cl, precision, flags=flags, d_manifold=1)
+    L.free()
+
+
+def test_curve_worked_example_on_the_gpu(mv):
+    """The paper's 5-point example (K = 4): rows (4, 19, -46, 19, 4)/35k^2 (MVGD, and the
+    divergence form on a straight line) and (2, -1, -2, -1, 2)/7k^2 (LS), in any direction."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_example_1d.json")))
+    for n_amb, k in ((2, 0.5), (3, 0.1)):
+        p = clouds.line_example(k, n_amb, direction=np.arange(1, n_amb + 1, dtype=float))
+        P = torch.tensor(p, device=DEV)
+        for flags, key, den in ((0, "mvgd_row_at_h_eq_k_times_35k2", 35.0),
+                                (mv.MVGD_FLAG_DIVERGENCE, "mvgd_row_at_h_eq_k_times_35k2", 35.0),
+                                (mv.MVGD_FLAG_LS, "ls_row_times_7k2", 7.0)):
+            L = mv.mvgd_assemble(P, 4, d_manifold=1, flags=flags)
+            rp, col, val = mv.mvgd_csr(L)
+            row = val.cpu().numpy().reshape(5, 5)[2]
+            want = np.array(g[key]) / (den * k * k)
+            assert list(col.cpu().numpy().reshape(5, 5)[2]) == [0, 1, 2, 3, 4]
+            np.testing.assert_allclose(row, want, rtol=0, atol=1e-12 * np.abs(want).max())
+            L.free()
+
+
+def test_curve_converges_on_the_gpu(mv):
+    """Unit circle, random sampling, FP64: the rms of Lf - Delta f falls with the sampling
+    density in both forms (the oracle's convergence pin, same inputs). FP64 because random
+    sampling puts near-coincident points on the curve: h and the row weights (~1/h^2) then span
+    many orders of magnitude, and float storage of the weights costs ~2^-24 sum_j |w_j f_j|."""
+    for flags in (0, mv.MVGD_FLAG_DIVERGENCE):
+        errs = []
+        for n in (500, 2000, 8000):
+            t = np.random.default_rng(n).uniform(0, 2 * np.pi, n)
+            P = torch.tensor(np.stack([np.cos(t), np.sin(t)], 1), device=DEV)
+            L = mv.mvgd_assemble(P, 6, d_manifold=1, flags=flags)
+            y = mv.mvgd_apply(L, torch.tensor(np.sin(2 * t), device=DEV))
+            e = y.cpu().numpy() + 4 * np.sin(2 * t)
+            errs.append(np.sqrt((e ** 2).mean()))
+            L.free()
+        assert errs[0] / errs[2] > 4.0, errs
+
+
 def test_exact_ties_on_a_lattice(mv):
     """Planar lattice: many equal distances; the tie-break (smaller index) must match."""
     g = np.stack(np.meshgrid(np.arange(40), np.arange(30), indexing="ij"), -1).reshape(-1, 2)
@@ -402,7 +466,6 @@ def test_host_pointer_rejected(mv):
 def test_allocation_failure_cleans_up(mv):
     """Every allocation of assemble/apply can fail: the call returns ENOMEM, leaks nothing that
     breaks later calls, and a clean call afterwards gives the same matrix."""
-    import os
     pts = torch.tensor(clouds.sphere(3000, 1, 20).points, device=DEV)
     ref = mv.mvgd_assemble(pts, 20)
     rc, cc, vc = mv.mvgd_csr(ref)
