@@ -211,3 +211,20 @@ def row_stats(row_ids, cols, vals):
               "max_ratio": float(ratio[ok].max()) if ok.any() else 0.0,
               "mean_ratio": float(ratio[ok].mean()) if ok.any() else 0.0}
     return {"ratio": ratio, "m_row": m_row, "diag_negative": diag_neg}, totals
+
+
+def solve(row_ptr, cols, vals, b, sigma: float = 0.0, pinned=()):
+    """Exact solution of A x = b with A = sigma I - L (L the CSR matrix), where every row listed
+    in `pinned` is replaced by the identity row (x_p = b_p): the systems of Sec. 4 (-Delta U = f
+    with sigma = 0 and one pinned value on a closed manifold). Sparse LU (SuperLU via scipy) as
+    the one library step; returns float64 [N]."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = len(row_ptr) - 1
+    L = sp.csr_matrix((np.asarray(vals, dtype=np.float64), np.asarray(cols),
+                       np.asarray(row_ptr)), shape=(n, n))
+    A = (sigma * sp.identity(n, format="csr") - L).tocsr()
+    keep = np.ones(n)
+    keep[list(pinned)] = 0.0
+    A = sp.diags(keep) @ A + sp.diags(1.0 - keep)
+    return spla.spsolve(A.tocsc(), np.asarray(b, dtype=np.float64))

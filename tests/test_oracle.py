@@ -568,3 +568,36 @@ def test_centre_modification_reduces_negative_mass(oracle_mod, cloud):
     assert tot["mvgd", 1.0]["mean_ratio"] < 0.1 * tot["ls", 1.0]["mean_ratio"]
     assert tot["mvgd", w]["n_m_rows"] > 0.3 * cl.n_points
     assert tot["ls", w]["n_m_rows"] < 0.01 * cl.n_points
+
+
+# ----------------------------------------------------------------------------------------
+# Linear solves with the assembled matrix (Sec. 4.2: -Delta U = 2x on the unit sphere)
+# ----------------------------------------------------------------------------------------
+def test_solve_sphere_position_converges(oracle_mod):
+    """-Delta U = 2x on the unit sphere has the solution U = x (up to a constant, fixed by one
+    pinned value): the discrete solution approaches x at about second order, as Sec. 4.2 reports."""
+    errs = []
+    for n in (1000, 4000):
+        cl = clouds.sphere(n, 5, 20)
+        P = cl.points
+        rp, c, v = oracle_mod.assemble(P, 20)
+        b = 2.0 * P[:, 0]
+        b[0] = P[0, 0]
+        x = oracle_mod.solve(rp, c, v, b, sigma=0.0, pinned=[0])
+        assert x[0] == pytest.approx(P[0, 0], abs=1e-12)
+        # the residual of the unpinned rows: (-L x)_i = b_i
+        r = -oracle_mod.apply(rp, c, v, x)[1:] - b[1:]
+        assert np.abs(r).max() <= 1e-8 * np.abs(v).max()
+        errs.append(np.abs(x - P[:, 0]).max())
+    assert errs[0] < 3e-3 and errs[0] / errs[1] > 2.5, errs
+
+
+def test_solve_screened_circle(oracle_mod):
+    """(sigma - Delta) U = f on an equispaced circle with U = sin 2t, f = (sigma + 4) sin 2t: the
+    solve reproduces U to the discretisation error, and a wrong sign of sigma would not."""
+    cl = clouds.circle(1000, 3, 6, sampling="uniform")
+    t = np.arctan2(cl.points[:, 1], cl.points[:, 0])
+    rp, c, v = oracle_mod.assemble(cl.points, 6, d=1)
+    for sigma in (1.0, 10.0):
+        x = oracle_mod.solve(rp, c, v, (sigma + 4.0) * np.sin(2 * t), sigma=sigma)
+        assert np.abs(x - np.sin(2 * t)).max() < 1e-6
