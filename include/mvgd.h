@@ -217,6 +217,45 @@ typedef struct {
 
 mvgd_status mvgd_row_stats(mvgd_matrix *L, double *ratio, mvgd_row_stats_t *out, void *stream);
 
+/*
+ * mvgd_solve -- iterative solution of (sigma I - L) x = b on the device (Sec. 4: the linear
+ * systems of the discretised Laplace-Beltrami equation, e.g. -Delta U = f with sigma = 0, and
+ * screened / implicit-diffusion systems with sigma > 0).
+ *
+ * Methods: BiCGSTAB (L is not symmetric), and damped Jacobi x += omega D^-1 (b - A x) with
+ * D = diag(A), the smoother the M-matrix property of the MVGD rows is meant to make convergent.
+ * With pin_first = 1 the first point of every cloud gets the identity row x_p = b_p (on closed
+ * manifolds L 1 = 0, so sigma = 0 is singular without it; put the wanted value at b_p).
+ *
+ * b      device, [n_rows] in the caller's order, the matrix dtype.
+ * x      device, [n_rows], the matrix dtype; in: initial guess, out: the last iterate.
+ * info   host; filled when the call returns (the call waits for `stream`).
+ * All iteration vectors and scalars are double and live on the device in the matrix's cell
+ * order; the host reads the residual once every check_every iterations. Inner products are
+ * reduced in a fixed order, so results are reproducible run to run.
+ * Returns MVGD_OK also when the iteration does not converge (see info->converged).
+ */
+enum { MVGD_SOLVE_BICGSTAB = 0, MVGD_SOLVE_JACOBI = 1 };
+
+typedef struct {
+    int32_t method;      /* MVGD_SOLVE_* */
+    int32_t max_iter;    /* >= 0 */
+    double rtol;         /* stop once ||r||_2 <= rtol ||b||_2 (the iteration's own residual) */
+    double sigma;        /* A = sigma I - L (finite) */
+    double omega;        /* Jacobi damping in (0, 2); 0 selects 2/3 */
+    int32_t pin_first;   /* 1: identity row at the first point of every cloud */
+    int32_t check_every; /* iterations enqueued between host residual checks; 0 selects 16 */
+} mvgd_solve_params;
+
+typedef struct {
+    int32_t iterations;   /* iterations (Jacobi: sweeps) performed */
+    int32_t converged;    /* 1: residual test passed, 0: max_iter reached, -1: breakdown */
+    double rel_residual;  /* ||b - A x||_2 / ||b||_2 of the returned x, recomputed */
+} mvgd_solve_info;
+
+mvgd_status mvgd_solve(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_params *p,
+                       mvgd_solve_info *info, void *stream);
+
 /* mvgd_pool_trim -- device memory of the current device that the library keeps cached. Handles
  * and assembly scratch come from a stream-ordered pool owned by the library, one per device; freed
  * memory stays in the pool for later calls (no fresh mapping per assembly). This call returns the

@@ -19,6 +19,7 @@
 #include "assemble.hpp"
 #include "bin.hpp"
 #include "common.hpp"
+#include "solve.hpp"
 #include "stats.hpp"
 
 using namespace mvgd;
@@ -807,6 +808,145 @@ mvgd_status mvgd_row_stats(mvgd_matrix *L, double *ratio, mvgd_row_stats_t *out,
     out->mean_ratio = nz > 0 ? tot.sum_ratio / (double)nz : 0.0;
     out->max_ratio = tot.max_ratio;
     return MVGD_OK;
+}
+
+} // extern "C"
+
+namespace {
+
+template <typename T>
+mvgd_status solve_impl(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_params &p,
+                       mvgd_solve_info *info, hipStream_t s)
+{
+    const int64_t n = L->n_total, ld = L->ld;
+    const int slots = L->K + 1;
+    const int nb = (int)((n + kSolveThreads - 1) / kSolveThreads);
+    const T *val = (const T *)L->ell_val;
+    const int32_t *col = L->ell_col;
+    const double sigma = p.sigma;
+    const int check = p.check_every > 0 ? p.check_every : 16;
+    const double omega = p.omega > 0.0 ? p.omega : 2.0 / 3.0;
+    const int is_double = sizeof(T) == 8;
+    // one allocation: 8 vectors, the partials, the scalars, the pinned-row mask
+    double *vb, *vx, *vr, *vrh, *vp, *vv, *vs, *vt, *part;
+    SolveScalars *sc;
+    uint8_t *pinned;
+    auto carve = [&](Carver &cv) {
+        for (double **v : {&vb, &vx, &vr, &vrh, &vp, &vv, &vs, &vt})
+            cv.take(*v, sizeof(double) * (size_t)n);
+        cv.take(part, sizeof(double) * 2 * (size_t)nb);
+        cv.take(sc, sizeof(SolveScalars));
+        cv.take(pinned, (size_t)n);
+    };
+    Carver sz;
+    carve(sz);
+    void *work = nullptr;
+    if (dev_alloc(&work, sz.off, s) != hipSuccess)
+        return fail(MVGD_ENOMEM, "device allocation failed (solver work, %zu bytes)", sz.off);
+    Carver cv{(char *)work, 0};
+    carve(cv);
+    struct Release {
+        void *w;
+        hipStream_t s;
+        ~Release() { (void)hipFreeAsync(w, s); }
+    } release_work{work, s};
+
+    solve_setup_kernel<<<nb, kSolveThreads, 0, s>>>(L->perm, L->grids, L->n_clouds, n, p.pin_first,
+                                                    b, x, is_double, vb, vx, pinned);
+    bicg_init_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma, vx, vb,
+                                                     vr, vrh, vp, vv, part);
+    solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepInit, part, nb, 2, sc, p.rtol);
+    double *xcur = vx;
+    SolveScalars hs;
+    memset(&hs, 0, sizeof hs);
+    auto read_scalars = [&]() {
+        return hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, s) == hipSuccess &&
+               hipStreamSynchronize(s) == hipSuccess;
+    };
+    if (p.method == MVGD_SOLVE_BICGSTAB) {
+        bicg_first_rho_kernel<<<1, 1, 0, s>>>(sc);
+        for (int it = 0; it < p.max_iter;) {
+            const int batch = std::min(check, p.max_iter - it);
+            for (int j = 0; j < batch; ++j, ++it) {
+                bicg_p_kernel<<<nb, kSolveThreads, 0, s>>>(n, vr, vv, vp, sc, it == 0);
+                bicg_v_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
+                                                              vp, vrh, vv, part, sc);
+                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepAlpha, part, nb, 1, sc, p.rtol);
+                bicg_s_kernel<<<nb, kSolveThreads, 0, s>>>(n, vr, vv, vs, sc);
+                bicg_t_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
+                                                              vs, vt, part, sc);
+                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepOmega, part, nb, 2, sc, p.rtol);
+                bicg_xr_kernel<<<nb, kSolveThreads, 0, s>>>(n, vp, vs, vt, vrh, vx, vr, part, sc);
+                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepRho, part, nb, 2, sc, p.rtol);
+            }
+            if (mvgd_status st = check_launch("solver"); st != MVGD_OK)
+                return st;
+            if (!read_scalars())
+                return fail(MVGD_EDEVICE, "reading the solver state failed");
+            if (hs.done)
+                break;
+        }
+    } else {
+        // damped Jacobi, ping-pong between vx and vp
+        for (int it = 0; it < p.max_iter;) {
+            const int batch = std::min(check, p.max_iter - it);
+            for (int j = 0; j < batch; ++j, ++it) {
+                const double *xi = (it % 2 == 0) ? vx : vp;
+                double *xo = (it % 2 == 0) ? vp : vx;
+                jacobi_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
+                                                              omega, vb, xi, xo, part, sc);
+                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepJacobi, part, nb, 1, sc, p.rtol);
+            }
+            if (mvgd_status st = check_launch("solver"); st != MVGD_OK)
+                return st;
+            if (!read_scalars())
+                return fail(MVGD_EDEVICE, "reading the solver state failed");
+            if (hs.done)
+                break;
+        }
+    }
+    if (!read_scalars())
+        return fail(MVGD_EDEVICE, "reading the solver state failed");
+    if (p.method == MVGD_SOLVE_JACOBI)
+        xcur = (hs.iters % 2 == 0) ? vx : vp; // the sweep count fixes the buffer of the last iterate
+    // the returned iterate's true residual, and the iterate in the caller's order
+    residual_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma, vb, xcur,
+                                                    part);
+    sum_partials_kernel<<<1, kSolveThreads, 0, s>>>(part, nb, &sc->dot[0]);
+    solve_scatter_kernel<<<nb, kSolveThreads, 0, s>>>(L->perm, n, xcur, x, is_double);
+    if (mvgd_status st = check_launch("solver"); st != MVGD_OK)
+        return st;
+    if (!read_scalars())
+        return fail(MVGD_EDEVICE, "reading the solver state failed");
+    info->iterations = hs.iters;
+    info->converged = hs.done == 1 ? 1 : hs.done == 2 ? -1 : 0;
+    info->rel_residual = hs.bb > 0.0 ? sqrt(hs.dot[0] / hs.bb) : sqrt(hs.dot[0]);
+    return MVGD_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+mvgd_status mvgd_solve(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_params *p,
+                       mvgd_solve_info *info, void *stream)
+{
+    if (!L || !b || !x || !p || !info)
+        return fail(MVGD_EINVAL, "NULL argument");
+    memset(info, 0, sizeof *info);
+    if (p->method != MVGD_SOLVE_BICGSTAB && p->method != MVGD_SOLVE_JACOBI)
+        return fail(MVGD_EINVAL, "unknown solver %d", p->method);
+    if (p->max_iter < 0 || !(p->rtol >= 0.0) || !std::isfinite(p->rtol) ||
+        !std::isfinite(p->sigma) || !(p->omega >= 0.0 && p->omega < 2.0) ||
+        (p->pin_first != 0 && p->pin_first != 1) || p->check_every < 0)
+        return fail(MVGD_EINVAL, "solver parameters out of range");
+    if (!is_device_pointer(b, L->device) || !is_device_pointer(x, L->device))
+        return fail(MVGD_EINVAL, "b and x must be device memory of the matrix's device");
+    hipStream_t s = (hipStream_t)stream;
+    L->stream = s;
+    if (L->precision == MVGD_FP64)
+        return solve_impl<double>(L, b, x, *p, info, s);
+    return solve_impl<float>(L, b, x, *p, info, s);
 }
 
 mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t)

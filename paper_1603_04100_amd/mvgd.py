@@ -25,7 +25,7 @@ MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 
 MVGD_FLAG_MLS, MVGD_FLAG_DIVERGENCE = 16, 32
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
-           "mvgd_timing", "mvgd_row_stats", "mvgd_pool_trim", "mvgd_status_str",
+           "mvgd_timing", "mvgd_row_stats", "mvgd_solve", "mvgd_pool_trim", "mvgd_status_str",
            "mvgd_last_error", "mvgd_version")
 
 
@@ -67,6 +67,21 @@ class mvgd_row_stats_t(ctypes.Structure):
                 ("max_ratio", ctypes.c_double)]
 
 
+MVGD_SOLVE_BICGSTAB, MVGD_SOLVE_JACOBI = 0, 1
+
+
+class mvgd_solve_params(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("omega", ctypes.c_double), ("pin_first", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class mvgd_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double)]
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"MVGD HIP library not built: {path} is missing "
@@ -90,6 +105,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mvgd_info.restype = i32
     lib.mvgd_row_stats.argtypes = [vp, vp, ctypes.POINTER(mvgd_row_stats_t), vp]
     lib.mvgd_row_stats.restype = i32
+    lib.mvgd_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mvgd_solve_params),
+                               ctypes.POINTER(mvgd_solve_info), vp]
+    lib.mvgd_solve.restype = i32
     lib.mvgd_pool_trim.argtypes = [ctypes.c_size_t]
     lib.mvgd_pool_trim.restype = i32
     lib.mvgd_status_str.argtypes = [i32]
@@ -240,6 +258,28 @@ def mvgd_row_stats(L: Matrix, ratio: bool = False, stream=None):
                                ctypes.byref(st), ctypes.c_void_p(_stream(stream))))
     out = {name: getattr(st, name) for name, _ in mvgd_row_stats_t._fields_}
     return (out, r) if ratio else out
+
+
+def mvgd_solve(L: Matrix, b: torch.Tensor, x: torch.Tensor | None = None, *,
+               method: str = "bicgstab", max_iter: int = 1000, rtol: float = 1e-10,
+               sigma: float = 0.0, omega: float = 0.0, pin_first: bool = False,
+               check_every: int = 0, stream=None):
+    """Solve (sigma I - L) x = b on the device; x (if given) is the initial guess and is
+    overwritten. Returns (x, info dict with iterations, converged, rel_residual)."""
+    if b.dtype != L.dtype or not b.is_contiguous() or b.numel() != L.n_rows:
+        raise ValueError("b must be a contiguous vector of the matrix dtype with n_rows entries")
+    if x is None:
+        x = torch.zeros_like(b)
+    elif x.dtype != L.dtype or not x.is_contiguous() or x.numel() != L.n_rows:
+        raise ValueError("x must be a contiguous vector of the matrix dtype with n_rows entries")
+    m = {"bicgstab": MVGD_SOLVE_BICGSTAB, "jacobi": MVGD_SOLVE_JACOBI}[method]
+    prm = mvgd_solve_params(m, int(max_iter), float(rtol), float(sigma), float(omega),
+                            1 if pin_first else 0, int(check_every))
+    info = mvgd_solve_info()
+    _check(_lib.mvgd_solve(L.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                           ctypes.byref(prm), ctypes.byref(info), ctypes.c_void_p(_stream(stream))))
+    return x, {"iterations": info.iterations, "converged": info.converged,
+               "rel_residual": info.rel_residual}
 
 
 def mvgd_pool_trim(keep_bytes: int = 0):

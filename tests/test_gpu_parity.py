@@ -322,6 +322,105 @@ def test_curve_converges_on_the_gpu(mv):
         assert errs[0] / errs[2] > 4.0, errs
 
 
+# ----------------------------------------------------------------------------------------------
+# iterative solves on the device against the exact (sparse LU) solution of the same system
+# ----------------------------------------------------------------------------------------------
+def _export_csr(mv, L, n, k):
+    rp, col, val = mv.mvgd_csr(L)
+    return (rp.cpu().numpy(), col.cpu().numpy().astype(np.int64),
+            val.cpu().numpy().astype(np.float64))
+
+
+def _cond_bound(rp, c, v, sigma, pinned):
+    """2-norm condition number of A = sigma I - L with pinned identity rows (dense SVD)."""
+    import scipy.sparse as sp
+    n = len(rp) - 1
+    A = (sigma * sp.identity(n) - sp.csr_matrix((v, c, rp), shape=(n, n))).toarray()
+    A[pinned] = 0.0
+    A[pinned, pinned] = 1.0
+    sv = np.linalg.svd(A, compute_uv=False)
+    return sv[0] / sv[-1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bicgstab_sphere_poisson(mv, precision):
+    """-Delta U = 2x on the unit sphere (Sec. 4.2), one pinned value: BiCGSTAB on the device
+    agrees with the exact solution of the same (exported) matrix to kappa(A) times the residual,
+    and the solution approaches x."""
+    cl = clouds.sphere(2000, 5, 20)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    P = torch.tensor(cl.points, dtype=dt, device=DEV)
+    L = mv.mvgd_assemble(P, 20)
+    pts = _oracle_points(cl.points, precision)
+    b = 2.0 * pts[:, 0]
+    b[0] = pts[0, 0]
+    rtol = 1e-12 if precision == "fp64" else 1e-6
+    x, info = mv.mvgd_solve(L, torch.tensor(b, dtype=dt, device=DEV), rtol=rtol, max_iter=3000,
+                            pin_first=True)
+    assert info["converged"] == 1, info
+    rp, c, v = _export_csr(mv, L, 2000, 20)
+    ref = oracle.solve(rp, c, v, b, sigma=0.0, pinned=[0])  # b is exact in either dtype
+    kappa = _cond_bound(rp, c, v, 0.0, [0])
+    got = x.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    store = 0.0 if precision == "fp64" else 2.0 ** -24  # the returned x is rounded to float
+    assert rel <= 10 * kappa * info["rel_residual"] + 4 * store, (rel, kappa, info)
+    assert np.abs(got - cl.points[:, 0]).max() < 5e-3
+    print(f"\n[bicgstab sphere 2k {precision}] {info}, kappa(A) {kappa:.3e}, |x - x_LU|/|x_LU| "
+          f"{rel:.2e}, max|x - x_exact| {np.abs(got - cl.points[:, 0]).max():.2e}")
+    # reproducible: the same solve twice gives the same bits
+    x2, info2 = mv.mvgd_solve(L, torch.tensor(b, dtype=dt, device=DEV), rtol=rtol, max_iter=3000,
+                              pin_first=True)
+    assert torch.equal(x, x2) and info == info2
+    L.free()
+
+
+def test_jacobi_screened_and_batched(mv):
+    """Damped Jacobi on (sigma I - L) x = b, sigma = 1000, two clouds in one handle (a pinned
+    first point in each): agrees with the exact block solution."""
+    cl = clouds.ellipsoid_batch(n_clouds=2, seed=41, k=20, n_min=1500, n_max=3000)
+    offs = [int(v) for v in cl.offsets]
+    n = cl.n_points
+    P = torch.tensor(cl.points, device=DEV)
+    L = mv.mvgd_assemble(P, 20, cloud_offsets=offs)
+    b = np.sin(3 * cl.points[:, 0]) + cl.points[:, 1]
+    x, info = mv.mvgd_solve(L, torch.tensor(b, device=DEV), method="jacobi", sigma=1000.0,
+                            rtol=1e-11, max_iter=20000, pin_first=True, check_every=200)
+    assert info["converged"] == 1, info
+    rp, c, v = _export_csr(mv, L, n, 20)
+    # columns of the export are local to each cloud: solve block by block
+    ref = np.empty(n)
+    for a, e in zip(offs[:-1], offs[1:]):
+        ref[a:e] = oracle.solve(rp[a:e + 1] - rp[a], c[rp[a]:rp[e]], v[rp[a]:rp[e]], b[a:e],
+                                sigma=1000.0, pinned=[0])
+    got = x.cpu().numpy()
+    assert got[offs[0]] == b[offs[0]] and got[offs[1]] == b[offs[1]]
+    kappa = max(_cond_bound(rp[a:e + 1] - rp[a], c[rp[a]:rp[e]], v[rp[a]:rp[e]], 1000.0, [0])
+                for a, e in zip(offs[:-1], offs[1:]))
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 10 * kappa * info["rel_residual"], (rel, kappa, info)
+    print(f"\n[jacobi sigma=1000, 2 clouds] {info}, kappa {kappa:.2e}, rel err {rel:.2e}")
+    L.free()
+
+
+def test_solver_on_ls_rows_reports_failure(mv):
+    """Plain least-squares rows (Sec. 4.1: not solvable by common iterative methods): Jacobi
+    diverges and is reported as not converged (breakdown or max_iter), without an error."""
+    cl = clouds.sphere(2000, 5, 20)
+    P = torch.tensor(cl.points, device=DEV)
+    L = mv.mvgd_assemble(P, 20, flags=mv.MVGD_FLAG_LS)
+    b = torch.tensor(2.0 * cl.points[:, 0], device=DEV)
+    x, info = mv.mvgd_solve(L, b, method="jacobi", max_iter=2000, rtol=1e-8, pin_first=True)
+    assert info["converged"] != 1, info
+    L.free()
+    L = mv.mvgd_assemble(P, 20)  # the MVGD rows with the same smoother: residual decreases
+    x, info2 = mv.mvgd_solve(L, b, method="jacobi", max_iter=2000, rtol=1e-8, pin_first=True)
+    assert info2["converged"] != -1 and info2["rel_residual"] < 1.0, info2
+    with pytest.raises(mv.MvgdError):
+        mv.mvgd_solve(L, b, method="jacobi", omega=2.5)  # damping outside (0, 2)
+    L.free()
+
+
 def test_exact_ties_on_a_lattice(mv):
     """Planar lattice: many equal distances; the tie-break (smaller index) must match."""
     g = np.stack(np.meshgrid(np.arange(40), np.arange(30), indexing="ij"), -1).reshape(-1, 2)
