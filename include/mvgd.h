@@ -225,7 +225,10 @@ mvgd_status mvgd_row_stats(mvgd_matrix *L, double *ratio, mvgd_row_stats_t *out,
  * Methods: BiCGSTAB (L is not symmetric), and damped Jacobi x += omega D^-1 (b - A x) with
  * D = diag(A), the smoother the M-matrix property of the MVGD rows is meant to make convergent.
  * With pin_first = 1 the first point of every cloud gets the identity row x_p = b_p (on closed
- * manifolds L 1 = 0, so sigma = 0 is singular without it; put the wanted value at b_p).
+ * manifolds L 1 = 0, so sigma = 0 is singular without it; put the wanted value at b_p). A
+ * Dirichlet condition on an open surface (Sec. 3.1: the condition is enforced at the boundary
+ * points, MVGD rows everywhere else) is the same identity row at every point flagged in
+ * `fixed`, with the boundary value in b.
  *
  * b      device, [n_rows] in the caller's order, the matrix dtype.
  * x      device, [n_rows], the matrix dtype; in: initial guess, out: the last iterate.
@@ -245,6 +248,8 @@ typedef struct {
     double omega;        /* Jacobi damping in (0, 2); 0 selects 2/3 */
     int32_t pin_first;   /* 1: identity row at the first point of every cloud */
     int32_t check_every; /* iterations enqueued between host residual checks; 0 selects 16 */
+    const uint8_t *fixed; /* device [n_rows] in the caller's order, nonzero = identity row
+                             (Dirichlet points); NULL for none */
 } mvgd_solve_params;
 
 typedef struct {

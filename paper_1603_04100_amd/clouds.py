@@ -10,6 +10,7 @@ remaining surfaces are synthetic stand-ins of the same kind, since the paper's p
 are not available):
 
 * ``sphere``           unit sphere in R^3, normalised standard Gaussian (uniform density).
+* ``hemisphere``       upper unit hemisphere with its boundary circle sampled (open surface).
 * ``circle``, ``helix`` curves (d = 1): the unit circle of Sec. 4.2 and an open helix in R^3.
 * ``torus``            torus in R^3 with tube-angle density proportional to 1 + 0.5 cos(theta).
 * ``ellipsoid_batch``  many ellipsoids of log-uniform size (batched assembly).
@@ -33,7 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "Cloud", "sphere", "circle", "helix", "torus", "ellipsoid_batch", "flat_torus4", "serving_stream",
+    "Cloud", "sphere", "hemisphere", "circle", "helix", "torus", "ellipsoid_batch", "flat_torus4", "serving_stream",
     "random_plane", "line_example", "sphere_harmonic", "implicit_laplacian",
     "ellipsoid_functions", "config", "CONFIGS",
 ]
@@ -98,6 +99,23 @@ def sphere(n: int = 2000, seed: int = 1, k: int = 20, degrees=(1,)) -> Cloud:
     f = np.stack([sphere_harmonic(p, l) for l in degrees], axis=1)
     lap = np.stack([-l * (l + 1) * sphere_harmonic(p, l) for l in degrees], axis=1)
     return _single("sphere", p, k, f, lap, seed=seed, degrees=list(degrees))
+
+
+def hemisphere(n: int = 4000, seed: int = 8, k: int = 20, n_boundary: int | None = None) -> Cloud:
+    """Upper unit hemisphere (Sec. 4.3's open surface): n random points with z > 0 plus
+    n_boundary (default ~ sqrt(pi n)) equispaced points on the boundary circle z = 0, listed last;
+    meta["boundary"] is the boundary mask. f = z: Delta f = -2 f and f = 0 on the boundary, so U = z
+    solves -Delta U = 2z with the Dirichlet condition U = 0."""
+    rng = np.random.default_rng(seed)
+    p = sphere_points(n, rng)
+    p[:, 2] = np.abs(p[:, 2])
+    nb = int(round(math.sqrt(math.pi * n))) if n_boundary is None else n_boundary
+    t = rng.uniform(0.0, 2.0 * np.pi) + 2.0 * np.pi * np.arange(nb) / nb
+    q = np.stack([np.cos(t), np.sin(t), np.zeros(nb)], axis=1)
+    pts = np.concatenate([p, q])
+    mask = np.zeros(len(pts), dtype=bool)
+    mask[n:] = True
+    return _single("hemisphere", pts, k, pts[:, 2], -2.0 * pts[:, 2], seed=seed, boundary=mask)
 
 
 # ----------------------------------------------------------------------------------------

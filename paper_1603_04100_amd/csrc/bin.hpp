@@ -4,8 +4,9 @@
 // plan_kernel      per-cloud cell grid and Morton part tables from the bounding boxes
 // key_kernel       cell key of every point and its slot inside the cell (atomic count)
 // scan_*           exclusive prefix sum of the cell counts -> cell start offsets
-// scatter_kernel   cell-sorted copy of the points (padded to 4 components), permutation and
-//                  its inverse (order inside a cell follows the atomic slots)
+// scatter_kernel   cell-sorted copy of the points (padded to 4 components) by the atomic slots
+// canon_kernel     canonical order inside every cell (ascending original index), permutation and
+//                  its inverse: the cell order is the same on every run
 #pragma once
 
 #include "common.hpp"
@@ -150,15 +151,15 @@ __global__ __launch_bounds__(256) void key_kernel(const T *__restrict__ pts,
     }
 }
 
+// First placement by the atomic slots (the order inside a cell depends on the race).
 template <typename T>
 __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts, int n_amb,
                                                       const CloudGrid *__restrict__ grids,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint32_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ slots,
-                                                      Pt<T> *__restrict__ spts,
-                                                      int32_t *__restrict__ perm,
-                                                      int32_t *__restrict__ iperm)
+                                                      Pt<T> *__restrict__ spts_tmp,
+                                                      int32_t *__restrict__ perm_tmp)
 {
     const CloudGrid g = grids[blockIdx.y];
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
@@ -168,10 +169,37 @@ __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts,
         Pt<T> p;
         for (int a = 0; a < 4; ++a)
             p.v[a] = a < n_amb ? pts[i * n_amb + a] : (T)0;
-        spts[pos] = p;
-        perm[pos] = (int32_t)i;
-        iperm[i] = (int32_t)pos;
+        spts_tmp[pos] = p;
+        perm_tmp[pos] = (int32_t)i;
     }
+}
+
+// Canonical order inside every cell: a point's final slot is the number of points of its cell
+// with a smaller original index (O(m) per point for a cell of m points; the neighbour search
+// already spends O(m) per query on such a cell). The result is the same on every run.
+template <typename T>
+__global__ __launch_bounds__(256) void canon_kernel(int64_t n_total,
+                                                    const uint32_t *__restrict__ cell_start,
+                                                    const uint32_t *__restrict__ keys,
+                                                    const Pt<T> *__restrict__ spts_tmp,
+                                                    const int32_t *__restrict__ perm_tmp,
+                                                    Pt<T> *__restrict__ spts,
+                                                    int32_t *__restrict__ perm,
+                                                    int32_t *__restrict__ iperm)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_total)
+        return;
+    const int32_t i = perm_tmp[s];
+    const uint32_t key = keys[i];
+    const uint32_t st = cell_start[key], en = cell_start[key + 1];
+    uint32_t rank = 0;
+    for (uint32_t t = st; t < en; ++t)
+        rank += perm_tmp[t] < i;
+    const int64_t dest = (int64_t)st + rank;
+    spts[dest] = spts_tmp[s];
+    perm[dest] = i;
+    iperm[i] = (int32_t)dest;
 }
 
 // ---------------------------------------------------------------------------------------------

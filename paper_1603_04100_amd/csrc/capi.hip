@@ -361,8 +361,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     CloudStats *d_stats;
     uint32_t *d_parts, *d_counts, *d_start, *d_keys, *d_slots;
     unsigned int *d_queue;
-    int32_t *d_iperm;
-    Pt<T> *d_spts;
+    int32_t *d_iperm, *d_perm_tmp;
+    Pt<T> *d_spts, *d_spts_tmp;
     std::vector<uint32_t *> lvl_sum(lvl_n.size()), lvl_off(lvl_n.size());
     auto carve_scratch = [&](Carver &cv) {
         cv.take(d_meta, sizeof(int64_t) * n_meta);
@@ -372,6 +372,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         cv.take(d_start, sizeof(uint32_t) * (cell_total + 1));
         cv.take(d_keys, sizeof(uint32_t) * n_total);
         cv.take(d_slots, sizeof(uint32_t) * n_total);
+        cv.take(d_spts_tmp, sizeof(Pt<T>) * n_total);
+        cv.take(d_perm_tmp, sizeof(int32_t) * n_total);
         cv.take(d_spts, sizeof(Pt<T>) * n_total);
         cv.take(d_queue, sizeof(unsigned int) * 8);
         cv.take(d_iperm, sizeof(int32_t) * n_total);
@@ -471,8 +473,10 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         scan_total_kernel<<<1, 64, 0, stream>>>(d_counts, d_start, cell_total);
     }
     scatter_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_start,
-                                                               d_keys, d_slots, d_spts, L->perm,
-                                                               d_iperm);
+                                                               d_keys, d_slots, d_spts_tmp,
+                                                               d_perm_tmp);
+    canon_kernel<T><<<(unsigned)((n_total + 255) / 256), 256, 0, stream>>>(
+        n_total, d_start, d_keys, d_spts_tmp, d_perm_tmp, d_spts, L->perm, d_iperm);
     if (mvgd_status st = check_launch("binning"); st != MVGD_OK)
         return st;
 
@@ -852,7 +856,7 @@ mvgd_status solve_impl(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_
     } release_work{work, s};
 
     solve_setup_kernel<<<nb, kSolveThreads, 0, s>>>(L->perm, L->grids, L->n_clouds, n, p.pin_first,
-                                                    b, x, is_double, vb, vx, pinned);
+                                                    p.fixed, b, x, is_double, vb, vx, pinned);
     bicg_init_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma, vx, vb,
                                                      vr, vrh, vp, vv, part);
     solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepInit, part, nb, 2, sc, p.rtol);
@@ -940,8 +944,9 @@ mvgd_status mvgd_solve(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_
         !std::isfinite(p->sigma) || !(p->omega >= 0.0 && p->omega < 2.0) ||
         (p->pin_first != 0 && p->pin_first != 1) || p->check_every < 0)
         return fail(MVGD_EINVAL, "solver parameters out of range");
-    if (!is_device_pointer(b, L->device) || !is_device_pointer(x, L->device))
-        return fail(MVGD_EINVAL, "b and x must be device memory of the matrix's device");
+    if (!is_device_pointer(b, L->device) || !is_device_pointer(x, L->device) ||
+        (p->fixed && !is_device_pointer(p->fixed, L->device)))
+        return fail(MVGD_EINVAL, "b, x and fixed must be device memory of the matrix's device");
     hipStream_t s = (hipStream_t)stream;
     L->stream = s;
     if (L->precision == MVGD_FP64)

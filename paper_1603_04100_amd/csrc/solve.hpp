@@ -2,9 +2,9 @@
 //
 // Everything runs in the matrix's cell order (the sliced-ELL order), in double: b and the initial
 // guess are permuted in once, the solution is permuted out once, and every operator application
-// is the coalesced ELL product of the apply path. Rows listed as pinned (the first point of every
-// cloud, on request) are identity rows, so x_p = b_p there; this removes the constant null
-// vector of L on closed manifolds (L 1 = 0).
+// is the coalesced ELL product of the apply path. Pinned rows (the first point of every cloud, on
+// request, and caller-flagged Dirichlet points) are identity rows, so x_p = b_p there; one per
+// cloud removes the constant null vector of L on closed manifolds (L 1 = 0).
 //
 // Inner products are reduced deterministically: every kernel that produces one writes one
 // partial per block (fixed tree over the block), and a single-block kernel adds the partials in
@@ -53,10 +53,12 @@ __device__ __forceinline__ void block_partials(double v[NP], double *out /* [NP]
 }
 
 // pinned[s] = 1 for the sorted position of the first caller row of every cloud (if requested)
+// and for every row flagged in `fixed` (caller order)
 __global__ __launch_bounds__(kSolveThreads) void solve_setup_kernel(
     const int32_t *__restrict__ perm, const CloudGrid *__restrict__ grids, int n_clouds, int64_t n,
-    int pin, const void *__restrict__ b, const void *__restrict__ x0, int is_double,
-    double *__restrict__ bs, double *__restrict__ xs, uint8_t *__restrict__ pinned)
+    int pin, const uint8_t *__restrict__ fixed, const void *__restrict__ b,
+    const void *__restrict__ x0, int is_double, double *__restrict__ bs, double *__restrict__ xs,
+    uint8_t *__restrict__ pinned)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n)
@@ -76,6 +78,8 @@ __global__ __launch_bounds__(kSolveThreads) void solve_setup_kernel(
         }
         pv = row == grids[lo].row0;
     }
+    if (fixed && fixed[row])
+        pv = 1;
     pinned[s] = pv;
 }
 

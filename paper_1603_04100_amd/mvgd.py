@@ -74,7 +74,7 @@ class mvgd_solve_params(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("omega", ctypes.c_double), ("pin_first", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("fixed", ctypes.c_void_p)]
 
 
 class mvgd_solve_info(ctypes.Structure):
@@ -263,9 +263,10 @@ def mvgd_row_stats(L: Matrix, ratio: bool = False, stream=None):
 def mvgd_solve(L: Matrix, b: torch.Tensor, x: torch.Tensor | None = None, *,
                method: str = "bicgstab", max_iter: int = 1000, rtol: float = 1e-10,
                sigma: float = 0.0, omega: float = 0.0, pin_first: bool = False,
-               check_every: int = 0, stream=None):
+               check_every: int = 0, fixed: torch.Tensor | None = None, stream=None):
     """Solve (sigma I - L) x = b on the device; x (if given) is the initial guess and is
-    overwritten. Returns (x, info dict with iterations, converged, rel_residual)."""
+    overwritten. fixed: optional uint8/bool device mask of identity rows (Dirichlet points,
+    x = b there). Returns (x, info dict with iterations, converged, rel_residual)."""
     if b.dtype != L.dtype or not b.is_contiguous() or b.numel() != L.n_rows:
         raise ValueError("b must be a contiguous vector of the matrix dtype with n_rows entries")
     if x is None:
@@ -273,8 +274,13 @@ def mvgd_solve(L: Matrix, b: torch.Tensor, x: torch.Tensor | None = None, *,
     elif x.dtype != L.dtype or not x.is_contiguous() or x.numel() != L.n_rows:
         raise ValueError("x must be a contiguous vector of the matrix dtype with n_rows entries")
     m = {"bicgstab": MVGD_SOLVE_BICGSTAB, "jacobi": MVGD_SOLVE_JACOBI}[method]
+    if fixed is not None:
+        fixed = fixed.to(torch.uint8).contiguous()
+        if fixed.numel() != L.n_rows or fixed.device != b.device:
+            raise ValueError("fixed must have n_rows entries on the matrix's device")
     prm = mvgd_solve_params(m, int(max_iter), float(rtol), float(sigma), float(omega),
-                            1 if pin_first else 0, int(check_every))
+                            1 if pin_first else 0, int(check_every),
+                            fixed.data_ptr() if fixed is not None else None)
     info = mvgd_solve_info()
     _check(_lib.mvgd_solve(L.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                            ctypes.byref(prm), ctypes.byref(info), ctypes.c_void_p(_stream(stream))))

@@ -106,6 +106,6 @@ def test_apply_and_free_accept_null_safely(mv):
     st = mv.mvgd_row_stats_t()
     assert lib.mvgd_row_stats(None, None, ctypes.byref(st), None) == -1
     assert lib.mvgd_pool_trim(0) in (0, -3)  # -3 (no device) on a host without a GPU
-    prm, info = mv.mvgd_solve_params(0, 10, 1e-8, 0.0, 0.0, 0, 0), mv.mvgd_solve_info()
+    prm, info = mv.mvgd_solve_params(0, 10, 1e-8, 0.0, 0.0, 0, 0, None), mv.mvgd_solve_info()
     assert lib.mvgd_solve(None, None, None, ctypes.byref(prm), ctypes.byref(info), None) == -1
     lib.mvgd_free(None)

@@ -375,6 +375,37 @@ def test_bicgstab_sphere_poisson(mv, precision):
     L.free()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bicgstab_hemisphere_dirichlet(mv, precision):
+    """Dirichlet points (identity rows at the sampled boundary circle) on the upper hemisphere:
+    -Delta U = 2z, U = 0 on the boundary; the device solution matches the sparse-LU solution of
+    the same matrix and approaches U = z."""
+    cl = clouds.hemisphere(4000, 8, 20)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    pts = _oracle_points(cl.points, precision)
+    m = cl.meta["boundary"]
+    P = torch.tensor(cl.points, dtype=dt, device=DEV)
+    L = mv.mvgd_assemble(P, 20)
+    b = 2.0 * pts[:, 2]
+    b[m] = 0.0
+    rtol = 1e-12 if precision == "fp64" else 1e-6
+    x, info = mv.mvgd_solve(L, torch.tensor(b, dtype=dt, device=DEV), rtol=rtol, max_iter=4000,
+                            fixed=torch.tensor(m, device=DEV))
+    assert info["converged"] == 1, info
+    rp, c, v = _export_csr(mv, L, cl.n_points, 20)
+    ref = oracle.solve(rp, c, v, b, pinned=np.nonzero(m)[0])
+    got = x.cpu().numpy().astype(np.float64)
+    assert np.abs(got[m]).max() <= 1e-12
+    kappa = _cond_bound(rp, c, v, 0.0, np.nonzero(m)[0])
+    store = 0.0 if precision == "fp64" else 2.0 ** -24
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel <= 10 * kappa * info["rel_residual"] + 4 * store, (rel, kappa, info)
+    assert np.abs(got - cl.points[:, 2]).max() < 5e-4
+    print(f"\n[dirichlet hemisphere 4k {precision}] {info}, kappa {kappa:.2e}, rel err {rel:.2e}, "
+          f"max|x - z| {np.abs(got - cl.points[:, 2]).max():.2e}")
+    L.free()
+
+
 def test_jacobi_screened_and_batched(mv):
     """Damped Jacobi on (sigma I - L) x = b, sigma = 1000, two clouds in one handle (a pinned
     first point in each): agrees with the exact block solution."""

@@ -601,3 +601,20 @@ def test_solve_screened_circle(oracle_mod):
     for sigma in (1.0, 10.0):
         x = oracle_mod.solve(rp, c, v, (sigma + 4.0) * np.sin(2 * t), sigma=sigma)
         assert np.abs(x - np.sin(2 * t)).max() < 1e-6
+
+
+def test_solve_hemisphere_dirichlet(oracle_mod):
+    """Open surface with the Dirichlet condition enforced at the boundary points and MVGD rows at
+    the interior points (Sec. 3.1): on the upper hemisphere -Delta U = 2z with U = 0 on the
+    boundary circle has the solution U = z; the discrete solution approaches it."""
+    errs = []
+    for n in (1000, 4000):
+        cl = clouds.hemisphere(n, 8, 20)
+        P, m = cl.points, cl.meta["boundary"]
+        rp, c, v = oracle_mod.assemble(P, 20)
+        b = 2.0 * P[:, 2]
+        b[m] = 0.0
+        x = oracle_mod.solve(rp, c, v, b, pinned=np.nonzero(m)[0])
+        assert np.abs(x[m]).max() <= 1e-10
+        errs.append(np.abs(x - P[:, 2]).max())
+    assert errs[0] < 1.5e-3 and errs[0] / errs[1] > 3.0, errs
