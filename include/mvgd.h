@@ -79,12 +79,19 @@ typedef struct {
     float radius_mu;       /* initial search radius / estimated K-th neighbour distance (1.7) */
     float cells_per_point; /* cell-table entries budgeted per point (8)                       */
     int32_t launch;        /* MVGD_LAUNCH_*                                                   */
+    int32_t search;        /* MVGD_SEARCH_*                                                   */
 } mvgd_params;
 
 enum {
     MVGD_LAUNCH_DEFAULT = 0,
     MVGD_LAUNCH_GRID = 1,      /* one workgroup per 64-point group, XCD-aware order */
     MVGD_LAUNCH_PERSISTENT = 2 /* resident workgroups popping groups from per-XCD queues */
+};
+
+enum {
+    MVGD_SEARCH_DEFAULT = 0,
+    MVGD_SEARCH_GROUP = 1, /* the 64 queries of a group stream their common cell box via LDS */
+    MVGD_SEARCH_LANE = 2   /* every query walks the cells of its own box */
 };
 
 typedef struct {
@@ -177,10 +184,13 @@ mvgd_status mvgd_csr(mvgd_matrix *L, int64_t *row_ptr, int32_t *col, void *val, 
 mvgd_status mvgd_row_diag(mvgd_matrix *L, double *h, uint8_t *status, void *stream);
 
 typedef struct {
-    float bin_ms;      /* assemble: bounding box, host planning gap, cell keys, scan, scatter */
-    float assemble_ms; /* assemble: the fused neighbour-search + fit + stencil kernel */
+    float bin_ms;      /* assemble: bounding boxes, grid plan, cell keys, scan, placement, the
+                          one synchronisation */
+    float assemble_ms; /* assemble: neighbour search + fit and stencil (search_ms + fit_ms) */
     float apply_ms;    /* last mvgd_apply: permutation of x + ELL SpMV */
     int32_t have_apply;
+    float search_ms;   /* assemble: the neighbour-search kernel */
+    float fit_ms;      /* assemble: the fit + stencil kernel */
 } mvgd_timing_t;
 
 /* mvgd_timing -- device durations measured with HIP events on the stream each call was enqueued

@@ -52,6 +52,7 @@ struct AsmParams {
     double w_nbr;               // least-squares weight of every neighbour (p_i: 1)
     double h_override;
     int64_t ld;                 // sliced-ELL leading dimension
+    int64_t n_rows;             // rows over all clouds
     int32_t *ell_col;           // [K+1][ld] sorted positions
     void *ell_val;              // [K+1][ld] weights (T)
     double *row_h;              // optional, sorted order
@@ -64,13 +65,22 @@ struct AsmParams {
 // LDS layout of one wave (bytes)
 constexpr int kLdsHist = 0;                                 // u32 [kBinWords][64] | f64 [kBndCap][64]
 constexpr int kLdsBndPos = kLdsHist + kBndCap * kWave * 8;  // i32 [kBndCap][64] (indices)
-constexpr int kLdsList = kLdsBndPos + kBndCap * kWave * 4;  // i32 [K][64]
+constexpr int kLdsSearch = kLdsBndPos + kBndCap * kWave * 4; // group search staging
 static_assert(kBinWords * kWave * 4 <= kBndCap * kWave * 8, "histogram must fit the key area");
 
-__host__ __device__ constexpr int lds_bytes(int K, int pt_bytes)
+// LDS of one search wave: histogram / boundary keys and indices, plus (group search) the cell
+// ranges, the staged points and the sub-group worklist
+__host__ __device__ constexpr int search_lds_bytes(int pt_bytes, bool group)
 {
-    return kLdsList + K * kWave * 4 /*list*/ + 2 * kWave * 4 /*cell ranges*/ +
-           kWave * pt_bytes + 2 * kWave * 4 /*staged pos, idx*/ + kWave * 8 /*sub-group worklist*/;
+    return kLdsSearch + (group ? 2 * kWave * 4 /*cell ranges*/ + kWave * pt_bytes +
+                                     2 * kWave * 4 /*staged pos, idx*/ + kWave * 8 /*worklist*/
+                               : 0);
+}
+
+// LDS of one fit wave: the neighbour list [K][64]
+__host__ __device__ constexpr int fit_lds_bytes(int K)
+{
+    return K * kWave * 4;
 }
 
 template <typename T, int NA>
@@ -719,29 +729,306 @@ __device__ __forceinline__ void fit_row(const AsmParams &P, const Pt<T> *spts,
     if (P.row_flags)
         P.row_flags[q] = (uint8_t)((degenerate ? 1 : 0) | (slow_row ? 2 : 0) | (close_pair ? 4 : 0));
     const unsigned long long nd = __popcll(__ballot(degenerate));
-    const unsigned long long ns = __popcll(__ballot(slow_row));
-    if (lane == __ffsll((long long)__ballot(true)) - 1) {
-        if (nd)
-            atomicAdd(&P.counters[0], nd);
-        if (ns)
-            atomicAdd(&P.counters[1], ns);
+    if (lane == __ffsll((long long)__ballot(true)) - 1 && nd)
+        atomicAdd(&P.counters[0], nd); // slow-path rows are counted by the search
+}
+
+// ---------------------------------------------------------------------------------------------
+// per-lane search: every lane walks the cells of its own box (no shared staging)
+// ---------------------------------------------------------------------------------------------
+// Walk every point of the cell box [lo, hi] of this lane's query and call
+// visit(f, point, sorted position) on it, f the culling distance (+inf for the query itself).
+// Lanes step in lockstep; each step either visits one point or moves to the next cell (x
+// fastest; Morton codes are advanced as dilated integers per axis). Returns the points visited.
+template <typename T, int NA, typename F>
+__device__ __forceinline__ int walk_box(const AsmParams &P, const CloudGrid &g, const int lo[3],
+                                        const int hi[3], const Pt<T> &qp, int q, bool act,
+                                        F &&visit)
+{
+    const Pt<T> *spts = (const Pt<T> *)P.spts;
+    const uint32_t *px = P.parts + g.part0;
+    const uint32_t *py = px + g.dim[0];
+    const uint32_t *pz = py + g.dim[1];
+    const uint32_t MX = px[g.dim[0] - 1], MY = py[g.dim[1] - 1], MZ = pz[g.dim[2] - 1];
+    const uint32_t mx0 = px[lo[0]], my0 = py[lo[1]];
+    uint32_t mx = mx0, my = my0, mz = pz[lo[2]];
+    int x = lo[0], y = lo[1], z = lo[2];
+    uint32_t t = 0, tend = 0;
+    bool more = act;
+    if (more) {
+        const uint32_t cell = (uint32_t)g.cell0 + (mx | my | mz);
+        t = P.cell_start[cell];
+        tend = P.cell_start[cell + 1];
+    }
+    int visited = 0;
+    while (__ballot(more) != 0) {
+        if (more) {
+            if (t < tend) {
+                const Pt<T> c = spts[t];
+                const float f = ((int)t != q) ? cull_dist<T, NA>(qp, c) : INFINITY;
+                visit(f, c, (int)t);
+                ++t;
+                ++visited;
+            } else {
+                if (x < hi[0]) {
+                    ++x;
+                    mx = ((mx | ~MX) + 1u) & MX;
+                } else {
+                    x = lo[0];
+                    mx = mx0;
+                    if (y < hi[1]) {
+                        ++y;
+                        my = ((my | ~MY) + 1u) & MY;
+                    } else {
+                        y = lo[1];
+                        my = my0;
+                        if (z < hi[2]) {
+                            ++z;
+                            mz = ((mz | ~MZ) + 1u) & MZ;
+                        } else {
+                            more = false;
+                        }
+                    }
+                }
+                if (more) {
+                    const uint32_t cell = (uint32_t)g.cell0 + (mx | my | mz);
+                    t = P.cell_start[cell];
+                    tend = P.cell_start[cell + 1];
+                }
+            }
+        }
+    }
+    return visited;
+}
+
+// The exact K-nearest selection of the group search, with per-lane boxes: pass 1 (histogram of
+// the culling distance over [0, R^2], R grown x1.3 per lane until the lane counts K), optional
+// refinement inside the K-th bin, pass 2 (sure neighbours / FP64-keyed boundary band) over the
+// box of the lane's own narrowed radius, exact resolution, exhaustive extraction on overflow.
+// The list (lst[k * ls], k < K) receives original indices.
+template <typename T, int NA>
+__device__ __forceinline__ void search_lane(const AsmParams &P, const CloudGrid &g, int lane,
+                                            bool valid, int q, const Pt<T> &qp, const T uq[3],
+                                            int qidx, uint32_t *hist, double *bndkey,
+                                            int32_t *bndpos, int32_t *lst, int64_t ls,
+                                            bool &slow_row, int &n_streamed, int &n_grow)
+{
+    const int K = P.K;
+    const float e = kRelBand;
+    auto lane_box = [&](double R, int lo_[3], int hi_[3]) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const double u = (double)uq[ax];
+            const double slack = 0.01 * g.cell + 2e-6 * fabs(u);
+            lo_[ax] = cell_coord<double>(u - R - slack, g.lo[ax], g.inv_cell, g.dim[ax]);
+            hi_[ax] = cell_coord<double>(u + R + slack, g.lo[ax], g.inv_cell, g.dim[ax]);
+        }
+    };
+    // ----- pass 1: histogram; each lane grows its own radius until it counts K ---------------
+    double R = g.r0;
+    float R2 = 0.f, s0b = 0.f;
+    int total = 0;
+    int box_lo[3] = {0, 0, 0}, box_hi[3] = {0, 0, 0};
+    bool need = valid, all = false;
+    for (int grow = 0; __ballot(need) != 0; ++grow) {
+        if (need) {
+            lane_box(R, box_lo, box_hi);
+            all = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
+            const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
+            R2 = (float)R2d;
+            if (!all)
+                R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
+            R2 = fmaxf(R2, 1e-30f);
+            s0b = (float)kBins / R2;
+            for (int w = 0; w < kBinWords; ++w)
+                hist[w * kWave + lane] = 0u;
+            total = 0;
+            if (grow > 0)
+                ++n_grow;
+        }
+        n_streamed += walk_box<T, NA>(P, g, box_lo, box_hi, qp, q, need,
+                      [&](float f, const Pt<T> &c, int pos) {
+                          if (f <= R2) {
+                              ++total;
+                              const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
+                              atomicAdd(&hist[(bb >> 1) * kWave + lane], 1u << ((bb & 1) * 16));
+                          }
+                      });
+        if (need && total < K && all)
+            atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
+        need = need && total < K && !all;
+        if (need)
+            R *= 1.3;
+    }
+    const bool act = valid;
+
+    // ----- locate the bin of the K-th neighbour ----------------------------------------------
+    const bool overflow = total >= 0xffff; // 16-bit counters saturated: exhaustive path
+    int below = 0, b0 = kBins - 1, in_b0 = 0;
+    {
+        int cum = 0;
+        bool found = false;
+        for (int w = 0; w < kBinWords; ++w) {
+            const uint32_t h = hist[w * kWave + lane];
+            const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+            if (!found) {
+                if (cum + c0 >= K) {
+                    found = true; b0 = 2 * w; below = cum; in_b0 = c0;
+                } else if (cum + c0 + c1 >= K) {
+                    found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
+                }
+                cum += c0 + c1;
+            }
+        }
+    }
+    const float wb = R2 / (float)kBins;
+    float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
+    // later passes: the box of this lane's narrowed radius
+    int nbox_lo[3] = {0, 0, 0}, nbox_hi[3] = {0, 0, 0};
+    {
+        const float hmax = overflow ? R2 : hi_f;
+        const double rn = sqrt((double)hmax * (1.0 + 4.0 * (double)e)) * (1.0 + 1e-5);
+        if (rn < R) {
+            lane_box(rn, nbox_lo, nbox_hi);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                nbox_lo[a] = box_lo[a];
+                nbox_hi[a] = box_hi[a];
+            }
+        }
+    }
+    // ----- optional refinement inside bin b0 -------------------------------------------------
+    const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
+    if (__ballot(refine) != 0) {
+        const float base_lo = lo_f;
+        const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
+        if (refine)
+            for (int w = 0; w < kBinWords; ++w)
+                hist[w * kWave + lane] = 0u;
+        n_streamed += walk_box<T, NA>(P, g, nbox_lo, nbox_hi, qp, q, refine,
+                      [&](float f, const Pt<T> &c, int pos) {
+                          if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
+                              return;
+                          int sb = (int)((f - base_lo) * s1);
+                          sb = sb < 0 ? 0 : (sb > kBins - 1 ? kBins - 1 : sb);
+                          atomicAdd(&hist[(sb >> 1) * kWave + lane], 1u << ((sb & 1) * 16));
+                      });
+        if (refine) {
+            int cum = below, b1 = kBins - 1;
+            bool found = false;
+            for (int w = 0; w < kBinWords; ++w) {
+                const uint32_t h = hist[w * kWave + lane];
+                const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                if (!found) {
+                    if (cum + c0 >= K) {
+                        found = true; b1 = 2 * w;
+                    } else if (cum + c0 + c1 >= K) {
+                        found = true; b1 = 2 * w + 1;
+                    }
+                    cum += c0 + c1;
+                }
+            }
+            const float w1 = (hi_f - base_lo) / (float)kBins;
+            const float nlo = base_lo + (float)b1 * w1;
+            const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
+            lo_f = nlo;
+            hi_f = nhi;
+        }
+    }
+    if (overflow) { // everything within R is a boundary candidate
+        lo_f = 0.f;
+        hi_f = R2;
+    }
+    // ----- pass 2: classify ------------------------------------------------------------------
+    const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
+    int nin = 0, nb = 0;
+    n_streamed += walk_box<T, NA>(P, g, nbox_lo, nbox_hi, qp, q, act,
+                  [&](float f, const Pt<T> &c, int pos) {
+                      if (f * (1.f + e) < lo_t) {
+                          if (nin < K)
+                              lst[nin * ls] = P.perm[pos];
+                          ++nin;
+                      } else if (f * (1.f - e) <= hi_t) {
+                          if (nb < kBndCap) {
+                              bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
+                              bndpos[nb * kWave + lane] = P.perm[pos];
+                          }
+                          ++nb;
+                      }
+                  });
+    if (act && nin >= K)
+        atomicAdd(&P.counters[2], 1ull); // cannot happen (fewer than K below the K-th bin)
+    const int r = K - nin;
+    const bool slow = act && (nb > kBndCap || nb < r || nin >= K);
+    // ----- resolve the boundary by exact (key, index) rank -----------------------------------
+    if (act && !slow) {
+        for (int bi = 0; bi < nb; ++bi) {
+            const double kb = bndkey[bi * kWave + lane];
+            const int pb = bndpos[bi * kWave + lane]; // original index
+            int rank = 0;
+            for (int bj = 0; bj < nb; ++bj) {
+                const double kj = bndkey[bj * kWave + lane];
+                if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
+                    ++rank;
+            }
+            if (rank < r)
+                lst[(nin + rank) * ls] = pb;
+        }
+    }
+    // ----- exhaustive extraction for lanes that need it --------------------------------------
+    if (__ballot(slow) != 0) {
+        const int nin_s = slow ? (nin < K ? nin : 0) : 0;
+        const int rr = slow ? K - nin_s : 0;
+        const float lo_s = (slow && nin < K) ? lo_t : 0.f;
+        const int rmax = seg_max(rr, kWave);
+        double last_k = -1.0;
+        int last_i = -1;
+        for (int sidx = 0; sidx < rmax; ++sidx) {
+            double best_k = INFINITY;
+            int best_i = 0x7fffffff, best_p = -1;
+            const bool want = slow && sidx < rr;
+            n_streamed += walk_box<T, NA>(P, g, nbox_lo, nbox_hi, qp, q, want,
+                          [&](float f, const Pt<T> &c, int pos) {
+                              if (!(f * (1.f - e) <= hi_t) || f * (1.f + e) < lo_s)
+                                  return;
+                              const double k = exact_key<T, NA>(qp, c);
+                              const int idx = P.perm[pos];
+                              const bool after = k > last_k || (k == last_k && idx > last_i);
+                              const bool better = k < best_k || (k == best_k && idx < best_i);
+                              if (after && better) {
+                                  best_k = k; best_i = idx; best_p = pos;
+                              }
+                          });
+            if (want) {
+                lst[(nin_s + sidx) * ls] = best_p < 0 ? qidx : best_i;
+                last_k = best_k;
+                last_i = best_i;
+                if (best_i == 0x7fffffff)
+                    atomicAdd(&P.counters[2], 1ull);
+            }
+        }
+        if (slow)
+            slow_row = true;
     }
 }
 
 // ---------------------------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------------------------
-template <typename T, int NA, int D>
-__device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t group, char *lds)
+template <typename T, int NA, int S>
+__device__ __forceinline__ void search_group(const AsmParams &P, const int64_t group, char *lds)
 {
     const int lane = lane_id();
     const int K = P.K;
-    char *lds_rng = lds + kLdsList + K * kWave * 4;
+    char *lds_rng = lds + kLdsSearch;
     char *lds_stage = lds_rng + 2 * kWave * 4;
     uint32_t *hist = (uint32_t *)(lds + kLdsHist);
     double *bndkey = (double *)(lds + kLdsHist);
     int32_t *bndpos = (int32_t *)(lds + kLdsBndPos);
-    int32_t *list = (int32_t *)(lds + kLdsList);
 
     int ci = 0;
     {
@@ -775,263 +1062,272 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
             cc[a] = cell_coord<T>(uq[a], g.lo[a], g.inv_cell, g.dim[a]);
         }
     }
-    // During selection the list holds original indices (the order of a cell's points in the
-    // sorted array depends on atomic slot order, so positions are not canonical); every slot
-    // holds a valid index before selection writes it.
+    // The selection writes original indices straight into the row's ELL column slots 1..K
+    // (lst[k * ls]); every slot holds a valid index before the selection writes it. Lanes past
+    // the end of the cloud write nothing.
     const int qidx = P.perm[q];
-    for (int k = 0; k < K; ++k)
-        list[k * kWave + lane] = qidx;
-
-    // ----- sub-groups: split the wave's points at Morton jumps while that shrinks the boxes ------
-    // Consecutive sorted points are compact except where the Morton curve jumps; a group that
-    // straddles a jump has a box far larger than either side. A worklist of lane ranges is split
-    // at the lane pair whose Morton codes differ in the highest bit, whenever the two halves'
-    // boxes hold fewer cells than the whole.
-    const uint32_t mc = morton_of(P.parts, g, cc[0], cc[1], cc[2]);
-    const uint32_t mnext = __shfl_down(mc, 1, kWave);
-    const int hb = (lane + 1 < cnt) ? (32 - (int)__clz((int)(mc ^ mnext))) : -1;
-    int2 *work = (int2 *)(lds_stage + kWave * sizeof(Pt<T>) + 2 * kWave * 4);
-    // Search box of a lane range for radius R: the range's bounding box in projected coordinates
-    // grown by R (plus 1% of a cell, covering rounding in the binning), rounded out to cells.
-    // Every point within distance R of a query of the range lies in it.
-    auto range_box = [&](int a, int b, double R, int lo_[3], int hi_[3]) {
-        const bool in = valid && lane >= a && lane < b;
-        int cells = 1;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            const double umn = seg_min(in ? (double)uq[ax] : INFINITY, kWave);
-            const double umx = seg_max(in ? (double)uq[ax] : -INFINITY, kWave);
-            const double slack = 0.01 * g.cell + 1e-6 * (fabs(umn) + fabs(umx));
-            lo_[ax] = uniform(cell_coord<double>(umn - R - slack, g.lo[ax], g.inv_cell, g.dim[ax]));
-            hi_[ax] = uniform(cell_coord<double>(umx + R + slack, g.lo[ax], g.inv_cell, g.dim[ax]));
-            cells *= hi_[ax] - lo_[ax] + 1;
-        }
-        return cells;
-    };
-    const double r0 = g.r0;
-    // split only ranges whose box exceeds twice a single query's box
-    const int split_min = (int)fmin(2.0 * pow(2.0 * r0 * g.inv_cell + 2.0, 3.0), 1e9);
+    int32_t *lst = P.ell_col + P.ld + q;
+    const int64_t ls = P.ld;
+    if (valid)
+        for (int k = 0; k < K; ++k)
+            lst[k * ls] = qidx;
 
     bool slow_row = false;
-    const float e = kRelBand;
     int n_streamed = 0, n_sub = 0, n_grow = 0;
-    int top = 1;
-    if (lane == 0)
-        work[0] = make_int2(0, cnt);
-    __syncthreads();
-    while (top > 0) {
-        --top;
-        const int ra = uniform(work[top].x), rb = uniform(work[top].y);
-        int box_lo[3], box_hi[3];
-        const int cells = range_box(ra, rb, r0, box_lo, box_hi);
-        if (rb - ra >= 2 && cells > split_min) {
-            const int key = (lane >= ra && lane < rb - 1) ? hb * 64 + (63 - lane) : -1;
-            const int sk = uniform(seg_max(key, kWave));
-            const int sl = 63 - (sk & 63); // split after lane sl
-            int t0[3], t1[3];
-            const int c1 = range_box(ra, sl + 1, r0, t0, t1);
-            const int c2 = range_box(sl + 1, rb, r0, t0, t1);
-            if (c1 + c2 < cells) {
-                __syncthreads();
-                if (lane == 0) {
-                    work[top] = make_int2(sl + 1, rb);
-                    work[top + 1] = make_int2(ra, sl + 1);
-                }
-                __syncthreads();
-                top += 2;
-                continue;
+    if constexpr (S == 1) {
+        n_sub = 1;
+        search_lane<T, NA>(P, g, lane, valid, q, qp, uq, qidx, hist, bndkey, bndpos, lst, ls,
+                           slow_row, n_streamed, n_grow);
+    } else {
+        // ----- sub-groups: split the wave's points at Morton jumps while that shrinks the boxes ------
+        // Consecutive sorted points are compact except where the Morton curve jumps; a group that
+        // straddles a jump has a box far larger than either side. A worklist of lane ranges is split
+        // at the lane pair whose Morton codes differ in the highest bit, whenever the two halves'
+        // boxes hold fewer cells than the whole.
+        const uint32_t mc = morton_of(P.parts, g, cc[0], cc[1], cc[2]);
+        const uint32_t mnext = __shfl_down(mc, 1, kWave);
+        const int hb = (lane + 1 < cnt) ? (32 - (int)__clz((int)(mc ^ mnext))) : -1;
+        int2 *work = (int2 *)(lds_stage + kWave * sizeof(Pt<T>) + 2 * kWave * 4);
+        // Search box of a lane range for radius R: the range's bounding box in projected coordinates
+        // grown by R (plus 1% of a cell, covering rounding in the binning), rounded out to cells.
+        // Every point within distance R of a query of the range lies in it.
+        auto range_box = [&](int a, int b, double R, int lo_[3], int hi_[3]) {
+            const bool in = valid && lane >= a && lane < b;
+            int cells = 1;
+    #pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const double umn = seg_min(in ? (double)uq[ax] : INFINITY, kWave);
+                const double umx = seg_max(in ? (double)uq[ax] : -INFINITY, kWave);
+                const double slack = 0.01 * g.cell + 1e-6 * (fabs(umn) + fabs(umx));
+                lo_[ax] = uniform(cell_coord<double>(umn - R - slack, g.lo[ax], g.inv_cell, g.dim[ax]));
+                hi_[ax] = uniform(cell_coord<double>(umx + R + slack, g.lo[ax], g.inv_cell, g.dim[ax]));
+                cells *= hi_[ax] - lo_[ax] + 1;
             }
-        }
-        const bool act = valid && lane >= ra && lane < rb;
-        ++n_sub;
-        // ----- pass 1: histogram; grow the radius until every active lane counts K -----------
-        double R = r0;
-        float R2 = 0.f, s0b = 0.f;
-        int total = 0;
-        for (int grow = 0;; ++grow) {
-            if (grow > 0) {
-                range_box(ra, rb, R, box_lo, box_hi);
-                ++n_grow;
-            }
-            bool all = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
-            const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
-            R2 = (float)R2d;
-            if (!all)
-                R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
-            R2 = fmaxf(R2, 1e-30f);
-            s0b = (float)kBins / R2;
-            for (int w = 0; w < kBinWords; ++w)
-                hist[w * kWave + lane] = 0u;
-            total = 0;
-            __syncthreads();
-            n_streamed += stream_box<T, NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, qp, q, act,
-                          [&](float f, const Pt<T> &c, int pos, int idx) {
-                              if (f <= R2) {
-                                  ++total;
-                                  const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
-                                  atomicAdd(&hist[(bb >> 1) * kWave + lane], 1u << ((bb & 1) * 16));
-                              }
-                          });
-            const bool short_lane = act && total < K;
-            if (__ballot(short_lane) == 0 || all) {
-                if (short_lane)
-                    atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
-                break;
-            }
-            R *= 1.3;
-        }
+            return cells;
+        };
+        const double r0 = g.r0;
+        // split only ranges whose box exceeds twice a single query's box
+        const int split_min = (int)fmin(2.0 * pow(2.0 * r0 * g.inv_cell + 2.0, 3.0), 1e9);
 
-        // ----- locate the bin of the K-th neighbour ------------------------------------------
-        const bool overflow = total >= 0xffff; // 16-bit counters saturated: exhaustive path
-        int below = 0, b0 = kBins - 1, in_b0 = 0;
-        {
-            int cum = 0;
-            bool found = false;
-            for (int w = 0; w < kBinWords; ++w) {
-                const uint32_t h = hist[w * kWave + lane];
-                const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
-                if (!found) {
-                    if (cum + c0 >= K) {
-                        found = true; b0 = 2 * w; below = cum; in_b0 = c0;
-                    } else if (cum + c0 + c1 >= K) {
-                        found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
+        const float e = kRelBand;
+        int top = 1;
+        if (lane == 0)
+            work[0] = make_int2(0, cnt);
+        __syncthreads();
+        while (top > 0) {
+            --top;
+            const int ra = uniform(work[top].x), rb = uniform(work[top].y);
+            int box_lo[3], box_hi[3];
+            const int cells = range_box(ra, rb, r0, box_lo, box_hi);
+            if (rb - ra >= 2 && cells > split_min) {
+                const int key = (lane >= ra && lane < rb - 1) ? hb * 64 + (63 - lane) : -1;
+                const int sk = uniform(seg_max(key, kWave));
+                const int sl = 63 - (sk & 63); // split after lane sl
+                int t0[3], t1[3];
+                const int c1 = range_box(ra, sl + 1, r0, t0, t1);
+                const int c2 = range_box(sl + 1, rb, r0, t0, t1);
+                if (c1 + c2 < cells) {
+                    __syncthreads();
+                    if (lane == 0) {
+                        work[top] = make_int2(sl + 1, rb);
+                        work[top + 1] = make_int2(ra, sl + 1);
                     }
-                    cum += c0 + c1;
+                    __syncthreads();
+                    top += 2;
+                    continue;
                 }
             }
-        }
-        const float wb = R2 / (float)kBins;
-        float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
-        // Later passes only need candidates with f <= hi (times the band): stream the box of the
-        // largest such radius over the range's lanes instead of the pass-1 box.
-        int nbox_lo[3], nbox_hi[3];
-        {
-            const float hmax = seg_max(act ? (overflow ? R2 : hi_f) : 0.f, kWave);
-            const double rn = sqrt((double)hmax * (1.0 + 4.0 * (double)e)) * (1.0 + 1e-5);
-            if (rn < R)
-                range_box(ra, rb, rn, nbox_lo, nbox_hi);
-            else
-                for (int a = 0; a < 3; ++a) {
-                    nbox_lo[a] = box_lo[a];
-                    nbox_hi[a] = box_hi[a];
+            const bool act = valid && lane >= ra && lane < rb;
+            ++n_sub;
+            // ----- pass 1: histogram; grow the radius until every active lane counts K -----------
+            double R = r0;
+            float R2 = 0.f, s0b = 0.f;
+            int total = 0;
+            for (int grow = 0;; ++grow) {
+                if (grow > 0) {
+                    range_box(ra, rb, R, box_lo, box_hi);
+                    ++n_grow;
                 }
-        }
-        // ----- optional refinement inside bin b0 ---------------------------------------------
-        const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
-        if (__ballot(refine) != 0) {
-            const float base_lo = lo_f;
-            const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
-            for (int w = 0; w < kBinWords; ++w)
-                hist[w * kWave + lane] = 0u;
-            __syncthreads();
-            n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, refine,
-                          [&](float f, const Pt<T> &c, int pos, int idx) {
-                              if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
-                                  return;
-                              int sb = (int)((f - base_lo) * s1);
-                              sb = sb < 0 ? 0 : (sb > kBins - 1 ? kBins - 1 : sb);
-                              atomicAdd(&hist[(sb >> 1) * kWave + lane], 1u << ((sb & 1) * 16));
-                          });
-            if (refine) {
-                int cum = below, b1 = kBins - 1;
+                bool all = true;
+    #pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
+                const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
+                R2 = (float)R2d;
+                if (!all)
+                    R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
+                R2 = fmaxf(R2, 1e-30f);
+                s0b = (float)kBins / R2;
+                for (int w = 0; w < kBinWords; ++w)
+                    hist[w * kWave + lane] = 0u;
+                total = 0;
+                __syncthreads();
+                n_streamed += stream_box<T, NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, qp, q, act,
+                              [&](float f, const Pt<T> &c, int pos, int idx) {
+                                  if (f <= R2) {
+                                      ++total;
+                                      const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
+                                      atomicAdd(&hist[(bb >> 1) * kWave + lane], 1u << ((bb & 1) * 16));
+                                  }
+                              });
+                const bool short_lane = act && total < K;
+                if (__ballot(short_lane) == 0 || all) {
+                    if (short_lane)
+                        atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
+                    break;
+                }
+                R *= 1.3;
+            }
+
+            // ----- locate the bin of the K-th neighbour ------------------------------------------
+            const bool overflow = total >= 0xffff; // 16-bit counters saturated: exhaustive path
+            int below = 0, b0 = kBins - 1, in_b0 = 0;
+            {
+                int cum = 0;
                 bool found = false;
                 for (int w = 0; w < kBinWords; ++w) {
                     const uint32_t h = hist[w * kWave + lane];
                     const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
                     if (!found) {
                         if (cum + c0 >= K) {
-                            found = true; b1 = 2 * w;
+                            found = true; b0 = 2 * w; below = cum; in_b0 = c0;
                         } else if (cum + c0 + c1 >= K) {
-                            found = true; b1 = 2 * w + 1;
+                            found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
                         }
                         cum += c0 + c1;
                     }
                 }
-                const float w1 = (hi_f - base_lo) / (float)kBins;
-                const float nlo = base_lo + (float)b1 * w1;
-                const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
-                lo_f = nlo;
-                hi_f = nhi;
             }
-        }
-        if (overflow) { // everything within R is a boundary candidate
-            lo_f = 0.f;
-            hi_f = R2;
-        }
-        // ----- pass 2: classify --------------------------------------------------------------
-        const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
-        int nin = 0, nb = 0;
-        n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, act,
-                      [&](float f, const Pt<T> &c, int pos, int idx) {
-                          if (f * (1.f + e) < lo_t) {
-                              if (nin < K)
-                                  list[nin * kWave + lane] = idx;
-                              ++nin;
-                          } else if (f * (1.f - e) <= hi_t) {
-                              if (nb < kBndCap) {
-                                  bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
-                                  bndpos[nb * kWave + lane] = idx;
-                              }
-                              ++nb;
-                          }
-                      });
-        if (act && nin >= K)
-            atomicAdd(&P.counters[2], 1ull); // cannot happen (fewer than K below the K-th bin)
-        const int r = K - nin;
-        const bool slow = act && (nb > kBndCap || nb < r || nin >= K);
-        // ----- resolve the boundary by exact (key, index) rank --------------------------------
-        if (act && !slow) {
-            for (int bi = 0; bi < nb; ++bi) {
-                const double kb = bndkey[bi * kWave + lane];
-                const int pb = bndpos[bi * kWave + lane]; // original index
-                int rank = 0;
-                for (int bj = 0; bj < nb; ++bj) {
-                    const double kj = bndkey[bj * kWave + lane];
-                    if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
-                        ++rank;
-                }
-                if (rank < r)
-                    list[(nin + rank) * kWave + lane] = pb;
+            const float wb = R2 / (float)kBins;
+            float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
+            // Later passes only need candidates with f <= hi (times the band): stream the box of the
+            // largest such radius over the range's lanes instead of the pass-1 box.
+            int nbox_lo[3], nbox_hi[3];
+            {
+                const float hmax = seg_max(act ? (overflow ? R2 : hi_f) : 0.f, kWave);
+                const double rn = sqrt((double)hmax * (1.0 + 4.0 * (double)e)) * (1.0 + 1e-5);
+                if (rn < R)
+                    range_box(ra, rb, rn, nbox_lo, nbox_hi);
+                else
+                    for (int a = 0; a < 3; ++a) {
+                        nbox_lo[a] = box_lo[a];
+                        nbox_hi[a] = box_hi[a];
+                    }
             }
-        }
-        // ----- exhaustive extraction for lanes that need it ----------------------------------
-        if (__ballot(slow) != 0) {
-            const int nin_s = slow ? (nin < K ? nin : 0) : 0;
-            const int rr = slow ? K - nin_s : 0;
-            const float lo_s = (slow && nin < K) ? lo_t : 0.f;
-            const int rmax = seg_max(rr, kWave);
-            double last_k = -1.0;
-            int last_i = -1;
-            for (int sidx = 0; sidx < rmax; ++sidx) {
-                double best_k = INFINITY;
-                int best_i = 0x7fffffff, best_p = -1;
-                const bool want = slow && sidx < rr;
-                n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, want,
+            // ----- optional refinement inside bin b0 ---------------------------------------------
+            const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
+            if (__ballot(refine) != 0) {
+                const float base_lo = lo_f;
+                const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
+                for (int w = 0; w < kBinWords; ++w)
+                    hist[w * kWave + lane] = 0u;
+                __syncthreads();
+                n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, refine,
                               [&](float f, const Pt<T> &c, int pos, int idx) {
-                                  if (!(f * (1.f - e) <= hi_t) || f * (1.f + e) < lo_s)
+                                  if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
                                       return;
-                                  const double k = exact_key<T, NA>(qp, c);
-                                  const bool after = k > last_k || (k == last_k && idx > last_i);
-                                  const bool better = k < best_k || (k == best_k && idx < best_i);
-                                  if (after && better) {
-                                      best_k = k; best_i = idx; best_p = pos;
-                                  }
+                                  int sb = (int)((f - base_lo) * s1);
+                                  sb = sb < 0 ? 0 : (sb > kBins - 1 ? kBins - 1 : sb);
+                                  atomicAdd(&hist[(sb >> 1) * kWave + lane], 1u << ((sb & 1) * 16));
                               });
-                if (want) {
-                    list[(nin_s + sidx) * kWave + lane] = best_p < 0 ? qidx : best_i;
-                    last_k = best_k;
-                    last_i = best_i;
-                    if (best_i == 0x7fffffff)
-                        atomicAdd(&P.counters[2], 1ull);
+                if (refine) {
+                    int cum = below, b1 = kBins - 1;
+                    bool found = false;
+                    for (int w = 0; w < kBinWords; ++w) {
+                        const uint32_t h = hist[w * kWave + lane];
+                        const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                        if (!found) {
+                            if (cum + c0 >= K) {
+                                found = true; b1 = 2 * w;
+                            } else if (cum + c0 + c1 >= K) {
+                                found = true; b1 = 2 * w + 1;
+                            }
+                            cum += c0 + c1;
+                        }
+                    }
+                    const float w1 = (hi_f - base_lo) / (float)kBins;
+                    const float nlo = base_lo + (float)b1 * w1;
+                    const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
+                    lo_f = nlo;
+                    hi_f = nhi;
                 }
             }
-            if (slow)
-                slow_row = true;
+            if (overflow) { // everything within R is a boundary candidate
+                lo_f = 0.f;
+                hi_f = R2;
+            }
+            // ----- pass 2: classify --------------------------------------------------------------
+            const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
+            int nin = 0, nb = 0;
+            n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, act,
+                          [&](float f, const Pt<T> &c, int pos, int idx) {
+                              if (f * (1.f + e) < lo_t) {
+                                  if (nin < K)
+                                      lst[nin * ls] = idx;
+                                  ++nin;
+                              } else if (f * (1.f - e) <= hi_t) {
+                                  if (nb < kBndCap) {
+                                      bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
+                                      bndpos[nb * kWave + lane] = idx;
+                                  }
+                                  ++nb;
+                              }
+                          });
+            if (act && nin >= K)
+                atomicAdd(&P.counters[2], 1ull); // cannot happen (fewer than K below the K-th bin)
+            const int r = K - nin;
+            const bool slow = act && (nb > kBndCap || nb < r || nin >= K);
+            // ----- resolve the boundary by exact (key, index) rank --------------------------------
+            if (act && !slow) {
+                for (int bi = 0; bi < nb; ++bi) {
+                    const double kb = bndkey[bi * kWave + lane];
+                    const int pb = bndpos[bi * kWave + lane]; // original index
+                    int rank = 0;
+                    for (int bj = 0; bj < nb; ++bj) {
+                        const double kj = bndkey[bj * kWave + lane];
+                        if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
+                            ++rank;
+                    }
+                    if (rank < r)
+                        lst[(nin + rank) * ls] = pb;
+                }
+            }
+            // ----- exhaustive extraction for lanes that need it ----------------------------------
+            if (__ballot(slow) != 0) {
+                const int nin_s = slow ? (nin < K ? nin : 0) : 0;
+                const int rr = slow ? K - nin_s : 0;
+                const float lo_s = (slow && nin < K) ? lo_t : 0.f;
+                const int rmax = seg_max(rr, kWave);
+                double last_k = -1.0;
+                int last_i = -1;
+                for (int sidx = 0; sidx < rmax; ++sidx) {
+                    double best_k = INFINITY;
+                    int best_i = 0x7fffffff, best_p = -1;
+                    const bool want = slow && sidx < rr;
+                    n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, want,
+                                  [&](float f, const Pt<T> &c, int pos, int idx) {
+                                      if (!(f * (1.f - e) <= hi_t) || f * (1.f + e) < lo_s)
+                                          return;
+                                      const double k = exact_key<T, NA>(qp, c);
+                                      const bool after = k > last_k || (k == last_k && idx > last_i);
+                                      const bool better = k < best_k || (k == best_k && idx < best_i);
+                                      if (after && better) {
+                                          best_k = k; best_i = idx; best_p = pos;
+                                      }
+                                  });
+                    if (want) {
+                        lst[(nin_s + sidx) * ls] = best_p < 0 ? qidx : best_i;
+                        last_k = best_k;
+                        last_i = best_i;
+                        if (best_i == 0x7fffffff)
+                            atomicAdd(&P.counters[2], 1ull);
+                    }
+                }
+                if (slow)
+                    slow_row = true;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     if (lane == 0) {
@@ -1039,11 +1335,31 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
         atomicAdd(&P.counters[4], (unsigned long long)n_streamed);
         atomicAdd(&P.counters[5], (unsigned long long)n_grow);
     }
-    // =============================== per-lane fit =============================================
-    if (!valid)
+    const unsigned long long ns = __popcll(__ballot(valid && slow_row));
+    if (lane == 0 && ns)
+        atomicAdd(&P.counters[1], ns);
+    if (valid && P.row_flags)
+        P.row_flags[q] = slow_row ? 2 : 0;
+}
+
+// Per-lane fit of one row (one wave per 64 consecutive rows in cell order): the neighbour list
+// of the search (original indices in ELL slots 1..K) is put in canonical order, ascending
+// original index (the order of the rows of V in the paper's normal equations), mapped back to
+// sorted positions for local gathers, and fitted (fit_row writes the finished ELL row).
+template <typename T, int NA, int D>
+__global__ __launch_bounds__(64) void fit_kernel(AsmParams P)
+{
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    int32_t *list = (int32_t *)lds;
+    const int lane = lane_id();
+    const int64_t q64 = (int64_t)blockIdx.x * kWave + lane;
+    if (q64 >= P.n_rows)
         return;
-    // canonical neighbour order: ascending original index (the order of the rows of V in the
-    // paper's normal equations), then back to sorted positions for local gathers
+    const int q = (int)q64;
+    const int K = P.K;
+    const int64_t ld = P.ld;
+    for (int k = 0; k < K; ++k)
+        list[k * kWave + lane] = P.ell_col[(int64_t)(k + 1) * ld + q];
     for (int a = 1; a < K; ++a) {
         const int v = list[a * kWave + lane];
         int b = a - 1;
@@ -1056,29 +1372,31 @@ __device__ __forceinline__ void assemble_group(const AsmParams &P, const int64_t
 #pragma unroll 4
     for (int k = 0; k < K; ++k)
         list[k * kWave + lane] = P.iperm[list[k * kWave + lane]];
-    fit_row<T, NA, D>(P, spts, list, lane, q, qp, slow_row);
+    const Pt<T> *spts = (const Pt<T> *)P.spts;
+    const bool slow_row = P.row_flags ? (P.row_flags[q] & 2) != 0 : false;
+    fit_row<T, NA, D>(P, spts, list, lane, q, spts[q], slow_row);
 }
 
 // Grid-mapped launch: one workgroup per group, XCD-aware remap (workgroups are dispatched to the
 // eight XCDs round-robin, so workgroup b runs on XCD b % 8; consecutive groups, which are
 // neighbours in space, go to the same XCD and share its L2).
-template <typename T, int NA, int D>
-__global__ __launch_bounds__(64) void assemble_kernel(AsmParams P)
+template <typename T, int NA, int S>
+__global__ __launch_bounds__(64) void search_kernel(AsmParams P)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const int64_t b = blockIdx.x;
     const int64_t group = (b & 7) * P.groups_per_xcd + (b >> 3);
     if (group >= P.n_groups)
         return;
-    assemble_group<T, NA, D>(P, group, lds);
+    search_group<T, NA, S>(P, group, lds);
 }
 
 // Persistent launch: as many workgroups as fit on the device at once; each pops groups from the
 // queue of its XCD (queue x owns groups [x * groups_per_xcd, (x + 1) * groups_per_xcd)) and,
 // when that queue is empty, steals from the others in turn. Every workgroup exits once all eight
 // queues are exhausted. The queue counters must be zero at launch.
-template <typename T, int NA, int D>
-__global__ __launch_bounds__(64) void assemble_persistent_kernel(AsmParams P)
+template <typename T, int NA, int S>
+__global__ __launch_bounds__(64) void search_persistent_kernel(AsmParams P)
 {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const int home = (int)(blockIdx.x & 7);
@@ -1095,7 +1413,7 @@ __global__ __launch_bounds__(64) void assemble_persistent_kernel(AsmParams P)
             t = (unsigned int)uniform((int)t);
             if ((int64_t)t >= len)
                 break;
-            assemble_group<T, NA, D>(P, base + t, lds);
+            search_group<T, NA, S>(P, base + t, lds);
             __syncthreads();
         }
     }

@@ -169,7 +169,8 @@ struct mvgd_matrix {
     void *xs = nullptr;
     size_t xs_bytes = 0;
     size_t bytes = 0;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr}; // MVGD_FLAG_TIME
+    // MVGD_FLAG_TIME: [0] start, [1] search start, [5] fit start, [2] assembly end, [3, 4] apply
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool have_apply = false;
 };
 
@@ -267,7 +268,7 @@ void *staging(size_t bytes)
 }
 
 // Occupancy of the persistent assembly kernel (blocks per CU) per (precision, n, K), queried once.
-std::atomic<int> g_occupancy[2][3][2][kMaxK + 1]; // [double][n - 2][d - 1][K]
+std::atomic<int> g_occupancy[2][3][2]; // [double][n - 2][lane search]
 std::atomic<int> g_n_cu{0};
 
 template <typename T>
@@ -511,24 +512,27 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.h_override = p.h_override;
     ap.w_nbr = (p.flags & MVGD_FLAG_MLS) ? 1.0 / (double)K : 1.0;
     ap.ld = L->ld;
+    ap.n_rows = n_total;
     ap.ell_col = L->ell_col;
     ap.ell_val = L->ell_val;
     ap.row_h = L->row_h;
     ap.row_flags = L->row_flags;
     ap.counters = L->counters;
     ap.queue = d_queue;
-    const size_t lds = (size_t)lds_bytes(K, (int)sizeof(Pt<T>));
+    const int d = p.d_manifold;
+    const int lane_search = p.search == MVGD_SEARCH_LANE ? 1 : 0;
+    const size_t lds = (size_t)search_lds_bytes((int)sizeof(Pt<T>), !lane_search);
     const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
     unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
-    const int d = p.d_manifold;
     if (persistent) {
-        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb - 2][d - 1][K];
+        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb - 2][lane_search];
         int per_cu = occ.load(), n_cu = g_n_cu.load();
         if (per_cu <= 0 || n_cu <= 0) {
-            const void *kern = n_amb == 4 ? (const void *)assemble_persistent_kernel<T, 4, 2>
-                             : d == 2 ? (const void *)assemble_persistent_kernel<T, 3, 2>
-                             : n_amb == 3 ? (const void *)assemble_persistent_kernel<T, 3, 1>
-                                          : (const void *)assemble_persistent_kernel<T, 2, 1>;
+#define MVGD_PK(NA_)                                                                              \
+    (lane_search ? (const void *)search_persistent_kernel<T, NA_, 1>                              \
+                 : (const void *)search_persistent_kernel<T, NA_, 0>)
+            const void *kern = n_amb == 4 ? MVGD_PK(4) : n_amb == 3 ? MVGD_PK(3) : MVGD_PK(2);
+#undef MVGD_PK
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess ||
                 hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
                 return fail(MVGD_EDEVICE, "occupancy query failed");
@@ -542,22 +546,42 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     }
     if (L->ev[1])
         (void)hipEventRecord(L->ev[1], stream);
-#define MVGD_LAUNCH(NA_, D_)                                                                      \
+    // neighbour search: lists of original indices into ELL slots 1..K
+#define MVGD_SEARCH(NA_)                                                                          \
     do {                                                                                          \
-        if (persistent)                                                                           \
-            assemble_persistent_kernel<T, NA_, D_><<<nblk, kWave, lds, stream>>>(ap);             \
+        if (persistent && lane_search)                                                            \
+            search_persistent_kernel<T, NA_, 1><<<nblk, kWave, lds, stream>>>(ap);                \
+        else if (persistent)                                                                      \
+            search_persistent_kernel<T, NA_, 0><<<nblk, kWave, lds, stream>>>(ap);                \
+        else if (lane_search)                                                                     \
+            search_kernel<T, NA_, 1><<<nblk, kWave, lds, stream>>>(ap);                           \
         else                                                                                      \
-            assemble_kernel<T, NA_, D_><<<nblk, kWave, lds, stream>>>(ap);                        \
+            search_kernel<T, NA_, 0><<<nblk, kWave, lds, stream>>>(ap);                           \
     } while (0)
-    if (d == 2 && n_amb == 3)
-        MVGD_LAUNCH(3, 2);
-    else if (d == 2)
-        MVGD_LAUNCH(4, 2);
+    if (n_amb == 4)
+        MVGD_SEARCH(4);
     else if (n_amb == 3)
-        MVGD_LAUNCH(3, 1);
+        MVGD_SEARCH(3);
     else
-        MVGD_LAUNCH(2, 1);
-#undef MVGD_LAUNCH
+        MVGD_SEARCH(2);
+#undef MVGD_SEARCH
+    if (mvgd_status st = check_launch("neighbour search"); st != MVGD_OK)
+        return st;
+    if (L->ev[5])
+        (void)hipEventRecord(L->ev[5], stream);
+    // fit and stencil, one wave per 64 rows
+    {
+        const unsigned fb = (unsigned)((n_total + kWave - 1) / kWave);
+        const size_t flds = (size_t)fit_lds_bytes(K);
+        if (d == 2 && n_amb == 3)
+            fit_kernel<T, 3, 2><<<fb, kWave, flds, stream>>>(ap);
+        else if (d == 2)
+            fit_kernel<T, 4, 2><<<fb, kWave, flds, stream>>>(ap);
+        else if (n_amb == 3)
+            fit_kernel<T, 3, 1><<<fb, kWave, flds, stream>>>(ap);
+        else
+            fit_kernel<T, 2, 1><<<fb, kWave, flds, stream>>>(ap);
+    }
     if (mvgd_status st = check_launch("assemble"); st != MVGD_OK)
         return st;
     if (L->ev[2])
@@ -597,6 +621,8 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
         return fail(MVGD_EINVAL, "h_override must be positive and finite");
     if (p->launch < MVGD_LAUNCH_DEFAULT || p->launch > MVGD_LAUNCH_PERSISTENT)
         return fail(MVGD_EINVAL, "unknown launch mode %d", p->launch);
+    if (p->search < MVGD_SEARCH_DEFAULT || p->search > MVGD_SEARCH_LANE)
+        return fail(MVGD_EINVAL, "unknown search mode %d", p->search);
     if (p->cell_alpha < 0.0f || p->radius_mu < 0.0f || p->cells_per_point < 0.0f ||
         !std::isfinite(p->cell_alpha) || !std::isfinite(p->radius_mu) ||
         !std::isfinite(p->cells_per_point) || (p->cells_per_point > 0.0f && p->cells_per_point < 0.25f) ||
@@ -964,7 +990,9 @@ mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t)
         return fail(MVGD_EDEVICE, "event synchronisation failed");
     memset(t, 0, sizeof *t);
     if (hipEventElapsedTime(&t->bin_ms, L->ev[0], L->ev[1]) != hipSuccess ||
-        hipEventElapsedTime(&t->assemble_ms, L->ev[1], L->ev[2]) != hipSuccess)
+        hipEventElapsedTime(&t->assemble_ms, L->ev[1], L->ev[2]) != hipSuccess ||
+        hipEventElapsedTime(&t->search_ms, L->ev[1], L->ev[5]) != hipSuccess ||
+        hipEventElapsedTime(&t->fit_ms, L->ev[5], L->ev[2]) != hipSuccess)
         return fail(MVGD_EDEVICE, "event timing failed");
     if (L->have_apply) {
         if (hipEventElapsedTime(&t->apply_ms, L->ev[3], L->ev[4]) != hipSuccess)

@@ -40,10 +40,12 @@ class mvgd_params(ctypes.Structure):
                 ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("h_override", ctypes.c_double),
                 ("cell_alpha", ctypes.c_float), ("radius_mu", ctypes.c_float),
-                ("cells_per_point", ctypes.c_float), ("launch", ctypes.c_int32)]
+                ("cells_per_point", ctypes.c_float), ("launch", ctypes.c_int32),
+                ("search", ctypes.c_int32)]
 
 
 MVGD_LAUNCH_DEFAULT, MVGD_LAUNCH_GRID, MVGD_LAUNCH_PERSISTENT = 0, 1, 2
+MVGD_SEARCH_DEFAULT, MVGD_SEARCH_GROUP, MVGD_SEARCH_LANE = 0, 1, 2
 
 
 class mvgd_info_t(ctypes.Structure):
@@ -57,7 +59,8 @@ class mvgd_info_t(ctypes.Structure):
 
 class mvgd_timing_t(ctypes.Structure):
     _fields_ = [("bin_ms", ctypes.c_float), ("assemble_ms", ctypes.c_float),
-                ("apply_ms", ctypes.c_float), ("have_apply", ctypes.c_int32)]
+                ("apply_ms", ctypes.c_float), ("have_apply", ctypes.c_int32),
+                ("search_ms", ctypes.c_float), ("fit_ms", ctypes.c_float)]
 
 
 class mvgd_row_stats_t(ctypes.Structure):
@@ -186,7 +189,8 @@ def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision
     t = tuning or {}
     p = mvgd_params(points.shape[1], d_manifold, k, prec, flags, float(h_override or 0.0),
                     float(t.get("cell_alpha", 0.0)), float(t.get("radius_mu", 0.0)),
-                    float(t.get("cells_per_point", 0.0)), int(t.get("launch", 0)))
+                    float(t.get("cells_per_point", 0.0)), int(t.get("launch", 0)),
+                    int(t.get("search", 0)))
     offs_ptr, n_clouds = None, 1
     if cloud_offsets is not None:
         offs = (ctypes.c_int64 * len(cloud_offsets))(*[int(v) for v in cloud_offsets])

@@ -659,6 +659,54 @@ def test_launch_modes_and_tuning_do_not_change_results(mv):
                 assert (a == b).all(), tuning
 
 
+def _lattice_with_ties():
+    g = np.stack(np.meshgrid(np.arange(40), np.arange(30), indexing="ij"), -1).reshape(-1, 2)
+    pts = np.concatenate([g * 0.5, np.zeros((g.shape[0], 1))], 1).astype(np.float64)
+    pts = pts @ np.linalg.qr(np.random.default_rng(1).standard_normal((3, 3)))[0].T
+    return np.ascontiguousarray(pts[np.random.default_rng(2).permutation(pts.shape[0])])
+
+
+@pytest.mark.parametrize("case", ["flat4-fp32", "flat4-fp64", "torus-fp32", "lattice-fp64",
+                                  "dups-fp32", "helix-fp64", "batch-fp32"])
+def test_search_modes_agree(mv, case):
+    """The per-lane search (every query walks its own cell box) and the group search (64 queries
+    stream their common box) select the same neighbours and give bit-identical matrices, on
+    clouds with exact ties, duplicates, curves and batches; and the oracle agrees on the sets."""
+    name, precision = case.split("-")
+    d, offs, k = 2, None, 20
+    if name == "flat4":
+        cl = clouds.flat_torus4(30000, 71, 32)
+        pts, k = cl.points, 32
+    elif name == "torus":
+        pts, k = clouds.torus(20000, 72, 24).points, 24
+    elif name == "lattice":
+        pts, k = _lattice_with_ties(), 12
+    elif name == "dups":
+        base = clouds.sphere(1500, 5, 16).points
+        pts = np.concatenate([base, base[:200], base[:50]])
+        pts, k = np.ascontiguousarray(pts[np.random.default_rng(3).permutation(len(pts))]), 16
+    elif name == "helix":
+        pts, k, d = clouds.helix(5000, 73, 8).points, 8, 1
+    else:
+        cl = clouds.ellipsoid_batch(n_clouds=5, seed=74, k=20, n_min=300, n_max=8000)
+        pts, offs = cl.points, [int(v) for v in cl.offsets]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    P = torch.tensor(pts, dtype=dt, device=DEV)
+    out = []
+    for search in (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_LANE):
+        for launch in (1, 2):
+            L = mv.mvgd_assemble(P, k, cloud_offsets=offs, d_manifold=d,
+                                 tuning={"search": search, "launch": launch})
+            rp, col, val = mv.mvgd_csr(L)
+            out.append((col.cpu().numpy(), val.cpu().numpy()))
+            L.free()
+    for c, v in out[1:]:
+        assert (c == out[0][0]).all() and (v == out[0][1]).all()
+    if offs is None:
+        oc, _ = oracle.rows(_oracle_points(pts, precision), k, d=d)
+        assert (out[0][0].reshape(-1, k + 1) == oc).all()
+
+
 # ----------------------------------------------------------------------------------------------
 # serving: results are the same alone and in the mix; admission under a tiny HBM budget
 # ----------------------------------------------------------------------------------------------
