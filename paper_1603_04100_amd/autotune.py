@@ -6,6 +6,8 @@ The tunables change only performance, never results (the neighbour search is exa
 * radius_mu        initial search radius relative to the same estimate
 * cells_per_point  cell-table budget per point (finer grids cost a larger table)
 * launch           1 = one workgroup per 64-point group, 2 = persistent per-XCD work queues
+* search           1 = the group's queries stream their common cell box, 2 = every query walks
+                   its own box
 
 ``tune`` times the assembly kernel (HIP events recorded by the library on its stream) over a
 grid of settings on a given workload and returns the fastest. ``main`` tunes the named
@@ -29,13 +31,15 @@ GRID = {
     "radius_mu": (1.4, 1.7, 2.0),
     "cells_per_point": (4.0, 8.0, 16.0),
     "launch": (1, 2),
+    "search": (1, 2),
 }
 
 _table = None
 
 
-def _key(n_ambient: int, k: int, precision: str) -> str:
-    return f"n{n_ambient}_k{k}_{precision}"
+def _key(n_ambient: int, k: int, precision: str, d_manifold: int = 2) -> str:
+    return f"n{n_ambient}_k{k}_{precision}" if d_manifold == 2 else \
+        f"n{n_ambient}_d{d_manifold}_k{k}_{precision}"
 
 
 def _load() -> dict:
@@ -49,9 +53,10 @@ def _load() -> dict:
     return _table
 
 
-def lookup(n_ambient: int, k: int, precision: str, points_per_cloud: int) -> dict:
+def lookup(n_ambient: int, k: int, precision: str, points_per_cloud: int,
+           d_manifold: int = 2) -> dict:
     """Tuned settings for this shape (nearest log2 size), or {} for the library defaults."""
-    entries = _load().get(_key(n_ambient, k, precision), {})
+    entries = _load().get(_key(n_ambient, k, precision, d_manifold), {})
     if not entries:
         return {}
     b = math.log2(max(points_per_cloud, 1))
@@ -60,7 +65,7 @@ def lookup(n_ambient: int, k: int, precision: str, points_per_cloud: int) -> dic
 
 
 def tune(points, k: int, cloud_offsets=None, reps: int = 3, grid: dict | None = None,
-         verbose: bool = False):
+         verbose: bool = False, d_manifold: int = 2):
     """Time the assembly kernel over the settings grid; return (best settings, all results)."""
     import torch
     from . import mvgd as mv
@@ -73,7 +78,7 @@ def tune(points, k: int, cloud_offsets=None, reps: int = 3, grid: dict | None = 
         times = []
         for r in range(reps + 1):
             L = mv.mvgd_assemble(points, k, cloud_offsets=cloud_offsets, tuning=settings,
-                                 flags=mv.MVGD_FLAG_TIME)
+                                 flags=mv.MVGD_FLAG_TIME, d_manifold=d_manifold)
             t = mv.mvgd_timing(L)
             mv.mvgd_free(L)
             if r > 0:  # first run warms the allocator pool
@@ -90,7 +95,8 @@ def tune(points, k: int, cloud_offsets=None, reps: int = 3, grid: dict | None = 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--workloads", nargs="+",
-                    default=["flat_torus4_1m", "torus_200k", "sphere_2k", "ellipsoids_256"])
+                    default=["flat_torus4_1m", "torus_200k", "sphere_2k", "ellipsoids_256",
+                             "circle_100k"])
     ap.add_argument("--precisions", nargs="+", default=["fp32", "fp64"])
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--reps", type=int, default=3)
@@ -112,12 +118,14 @@ def main():
             dt = torch.float32 if prec == "fp32" else torch.float64
             P = torch.tensor(cl.points.astype(np.float32 if prec == "fp32" else np.float64),
                              device="cuda:0")
-            best, res = tune(P, cl.k, cloud_offsets=offs, reps=args.reps)
+            d = cl.meta.get("d", 2)
+            best, res = tune(P, cl.k, cloud_offsets=offs, reps=args.reps, d_manifold=d)
             default_ms = next(ms for ms, s in res if s == {"cell_alpha": 0.6, "radius_mu": 1.7,
-                                                           "cells_per_point": 8.0, "launch": 1})
+                                                           "cells_per_point": 8.0, "launch": 1,
+                                                           "search": 1})
             print(f"[autotune] {name} {prec}: best {res[0][0]:.3f} ms {best} "
                   f"(defaults {default_ms:.3f} ms)", flush=True)
-            key = _key(cl.n_ambient, cl.k, prec)
+            key = _key(cl.n_ambient, cl.k, prec, d)
             table.setdefault(key, {})[f"{math.log2(per_cloud):.2f}"] = {
                 "settings": best, "ms": res[0][0], "default_ms": default_ms, "workload": name,
                 "points_per_cloud": per_cloud}

@@ -185,7 +185,8 @@ def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision
         from . import autotune
         tuning = autotune.lookup(points.shape[1], k, precision,
                                  points.shape[0] if cloud_offsets is None
-                                 else points.shape[0] // max(1, len(cloud_offsets) - 1))
+                                 else points.shape[0] // max(1, len(cloud_offsets) - 1),
+                                 d_manifold)
     t = tuning or {}
     p = mvgd_params(points.shape[1], d_manifold, k, prec, flags, float(h_override or 0.0),
                     float(t.get("cell_alpha", 0.0)), float(t.get("radius_mu", 0.0)),
