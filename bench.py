@@ -8,10 +8,11 @@ one mvgd_apply of f, with the points already resident in HBM.
 
 Prints ONE JSON line (rank 0, N = 1):
   value        rows/s of the FP32-mixed path = N / (wall time per step)
-  roofline     the dominant kernel (the fused assembly kernel): algorithmic bytes per launch
-               (point read + ELL write) / its average duration from HIP events recorded by the
-               library on the launch stream, against 8 TB/s; traffic from committed rocprofv3
-               counter summaries when they match the current kernel sources, else null
+  roofline     the dominant work, the assembly (neighbour-search kernel + fit kernel, launched
+               back to back): algorithmic bytes per assembly (point read + ELL write) / its
+               average duration from HIP events recorded by the library on the launch stream,
+               against 8 TB/s; traffic from committed rocprofv3 counter summaries of the two
+               kernels when they match the current kernel sources, else null
   cpu_baseline the FP64 oracle (brute-force kNN + QR, OpenMP over rows) on a bounded sample of rows
                of the same cloud, on the host cores
 """
@@ -339,14 +340,18 @@ def main():
               "MVGD rows/s, batched assembly of many clouds in one launch + apply of 4 RHS")
     achieved = bytes_per_row * n / (asm32 * 1e-3) / 1e9
     from paper_1603_04100_amd import autotune
-    launch = autotune.lookup(cl.n_ambient, k, "fp32", n // (cl.offsets.shape[0] - 1)).get("launch", 1)
-    kernel_name = (f"assemble_persistent_kernel<float,{cl.n_ambient}>" if launch == 2 else
-                   f"assemble_kernel<float,{cl.n_ambient}>")
+    tun = autotune.lookup(cl.n_ambient, k, "fp32", n // (cl.offsets.shape[0] - 1))
+    search = "search_persistent_kernel" if tun.get("launch", 1) == 2 else "search_kernel"
+    kernel_name = (f"{search}<float,{cl.n_ambient},{1 if tun.get('search', 1) == 2 else 0}> + "
+                   f"fit_kernel<float,{cl.n_ambient},2>")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": counter_traffic(args.workload, "fp32", n),
             "kernel": kernel_name, "kernel_ms": round(asm32, 4),
+            "search_ms": round(float(np.mean([t["search_ms"] for t in tk32])), 4),
+            "fit_ms": round(float(np.mean([t["fit_ms"] for t in tk32])), 4),
             "algorithmic_bytes_per_row": bytes_per_row}
+    dev_step = np.array([t["bin_ms"] + t["assemble_ms"] + t["apply_ms"] for t in tk32])
     out = {
         "metric": metric,
         "value": n / t32, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
@@ -362,6 +367,8 @@ def main():
         "fp64": fp64,
         "variants_fp32": variants,
         "kernels_ms": {"bin": bin32, "assemble": asm32, "apply": app32},
+        "device_step_ms": {"p50": float(np.percentile(dev_step, 50)),
+                           "p99": float(np.percentile(dev_step, 99))},
         "accuracy": acc,
         "kernel_source_hash": kernel_source_hash(),
     }
