@@ -1063,14 +1063,11 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
         }
     }
     // The selection writes original indices straight into the row's ELL column slots 1..K
-    // (lst[k * ls]); every slot holds a valid index before the selection writes it. Lanes past
-    // the end of the cloud write nothing.
+    // (lst[k * ls]); lanes past the end of the cloud write nothing. (Every slot is written; the
+    // fit kernel still range-checks what it reads.)
     const int qidx = P.perm[q];
     int32_t *lst = P.ell_col + P.ld + q;
     const int64_t ls = P.ld;
-    if (valid)
-        for (int k = 0; k < K; ++k)
-            lst[k * ls] = qidx;
 
     bool slow_row = false;
     int n_streamed = 0, n_sub = 0, n_grow = 0;
@@ -1358,8 +1355,11 @@ __global__ __launch_bounds__(64) void fit_kernel(AsmParams P)
     const int q = (int)q64;
     const int K = P.K;
     const int64_t ld = P.ld;
-    for (int k = 0; k < K; ++k)
-        list[k * kWave + lane] = P.ell_col[(int64_t)(k + 1) * ld + q];
+    const int qidx = P.perm[q];
+    for (int k = 0; k < K; ++k) {
+        const int idx = P.ell_col[(int64_t)(k + 1) * ld + q];
+        list[k * kWave + lane] = (idx >= 0 && (int64_t)idx < P.n_rows) ? idx : qidx;
+    }
     for (int a = 1; a < K; ++a) {
         const int v = list[a * kWave + lane];
         int b = a - 1;
