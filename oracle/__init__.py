@@ -228,3 +228,94 @@ def solve(row_ptr, cols, vals, b, sigma: float = 0.0, pinned=()):
     keep[list(pinned)] = 0.0
     A = sp.diags(keep) @ A + sp.diags(1.0 - keep)
     return spla.spsolve(A.tocsc(), np.asarray(b, dtype=np.float64))
+
+
+def neumann_ghosts(points, boundary, k: int, k_boundary: int):
+    """Ghost points of the reflection method for the Neumann condition on an open surface in R^3
+    (Sec. 3.1), step by step:
+
+    * interior points P^I (boundary == False), boundary points P^B;
+    * an interior point gets a ghost if one of its K nearest neighbours in the whole cloud is a
+      boundary point (O1 kNN);
+    * p^B_j = its closest boundary point (FP64 squared distance, ties to the smaller index);
+    * at p^B_j: the boundary curve through its k_boundary nearest boundary points (p^B_j
+      included) as (xi, eta(xi), zeta(xi)) in their PCA frame, quadratic least squares; its
+      tangent at p^B_j is e1 = (1, eta'(xi_j), zeta'(xi_j)) back in ambient coordinates,
+      normalised; e2 = the surface normal, the smallest-eigenvalue eigenvector of the covariance
+      of the K nearest neighbours of p^B_j in the whole cloud; e3 = e1 x e2 (normalised);
+    * the ghost is the mirror image p^R = p^I - 2 ((p^I - p^B_j) . e3) e3.
+
+    Returns (interior indices [NI], ghost points [NG, 3], ghost source = index into the interior
+    list [NG], ghost boundary point index [NG]); ghosts are listed in the order of their source.
+    """
+    P = _points(points)
+    B = np.asarray(boundary, dtype=bool)
+    n = P.shape[0]
+    interior = np.nonzero(~B)[0]
+    bidx = np.nonzero(B)[0]
+    nbr, _ = knn(P, k)
+    has_b = B[nbr].any(axis=1)
+    src_i = [r for r, i in enumerate(interior) if has_b[i]]
+    PB = P[bidx]
+    # the frames at the boundary points that are used
+    frames = {}
+
+    def frame(j):
+        if j in frames:
+            return frames[j]
+        d2 = ((PB - PB[j]) ** 2).sum(1)
+        order = np.lexsort((np.arange(len(PB)), d2))[:k_boundary]
+        Q = PB[order]
+        c = Q.mean(0)
+        w, V = np.linalg.eigh((Q - c).T @ (Q - c))
+        t, n1, n2 = V[:, 2], V[:, 1], V[:, 0]
+        xi = (Q - PB[j]) @ t
+        A = np.stack([np.ones_like(xi), xi, xi * xi], 1)
+        ce = np.linalg.lstsq(A, (Q - PB[j]) @ n1, rcond=None)[0]
+        cz = np.linalg.lstsq(A, (Q - PB[j]) @ n2, rcond=None)[0]
+        e1 = t + ce[1] * n1 + cz[1] * n2  # derivative of the fitted curve at xi = 0 (p^B_j)
+        e1 /= np.linalg.norm(e1)
+        nb = nbr[bidx[j]]
+        D = P[nb] - P[nb].mean(0)
+        e2 = np.linalg.eigh(D.T @ D)[1][:, 0]
+        e3 = np.cross(e1, e2)
+        e3 /= np.linalg.norm(e3)
+        frames[j] = e3
+        return e3
+
+    ghosts, bsrc = [], []
+    for r in src_i:
+        p = P[interior[r]]
+        d2 = ((PB - p) ** 2).sum(1)
+        j = int(np.lexsort((np.arange(len(PB)), d2))[0])
+        e3 = frame(j)
+        ghosts.append(p - 2.0 * np.dot(p - PB[j], e3) * e3)
+        bsrc.append(bidx[j])
+    return (interior, np.array(ghosts).reshape(-1, 3), np.array(src_i, dtype=np.int64),
+            np.array(bsrc, dtype=np.int64))
+
+
+def neumann_rows(points, boundary, k: int, k_boundary: int, ghosts=None, nthreads: int = 0):
+    """MVGD rows of the interior points with the homogeneous Neumann condition (Sec. 3.1): the
+    rows of the augmented cloud P^I u P^R, every ghost column folded into its source interior
+    point (U(p^R) = U(p^I) when the normal derivative is zero). `ghosts` (the output of
+    neumann_ghosts) may be given to assemble on exactly those ghost points.
+    Returns (row_ptr, cols, vals) over the NI interior points, columns = interior list indices
+    (a folded ghost shares its source's column; duplicates are merged), plus the ghost tuple."""
+    P = _points(points)
+    g = neumann_ghosts(P, boundary, k, k_boundary) if ghosts is None else ghosts
+    interior, G, src = g[0], g[1], g[2]
+    ni = len(interior)
+    A = np.concatenate([P[interior], G]) if len(G) else P[interior]
+    cols, vals = rows(A, k, rows=np.arange(ni), nthreads=nthreads)
+    fold = np.concatenate([np.arange(ni), src])
+    rp, cc, vv = [0], [], []
+    for r in range(ni):
+        merged = {}
+        for c, v in zip(fold[cols[r]], vals[r]):
+            merged[int(c)] = merged.get(int(c), 0.0) + v
+        keys = sorted(merged)
+        cc.extend(keys)
+        vv.extend(merged[c] for c in keys)
+        rp.append(len(cc))
+    return np.array(rp, dtype=np.int64), np.array(cc, dtype=np.int64), np.array(vv), g

@@ -618,3 +618,56 @@ def test_solve_hemisphere_dirichlet(oracle_mod):
         assert np.abs(x[m]).max() <= 1e-10
         errs.append(np.abs(x - P[:, 2]).max())
     assert errs[0] < 1.5e-3 and errs[0] / errs[1] > 3.0, errs
+
+
+# ----------------------------------------------------------------------------------------
+# Neumann condition by reflection (Sec. 3.1)
+# ----------------------------------------------------------------------------------------
+def _half_square(n=1500, seed=9, nb=60):
+    """Points of the square [0, 1]^2 (plane z = 0, rotated into R^3) with the edge x = 0 sampled
+    as the boundary (listed last)."""
+    rng = np.random.default_rng(seed)
+    q = rng.uniform(0.0, 1.0, (n, 2))
+    q[:, 0] = 0.02 + 0.98 * q[:, 0]
+    b = np.stack([np.zeros(nb), (np.arange(nb) + 0.5) / nb], 1)
+    pts = np.concatenate([q, b])
+    R = np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    P = np.concatenate([pts, np.zeros((len(pts), 1))], 1) @ R.T + rng.standard_normal(3)
+    mask = np.zeros(len(pts), dtype=bool)
+    mask[n:] = True
+    return P, mask, pts, R
+
+
+def test_neumann_ghosts_mirror_a_straight_boundary(oracle_mod):
+    """With a straight boundary line in a plane the boundary frame is exact, and every ghost is
+    the mirror image of its source across the line: (x, y) -> (-x, y)."""
+    P, mask, pts, R = _half_square()
+    interior, G, src, bsrc = oracle_mod.neumann_ghosts(P, mask, 16, 6)
+    assert len(G) > 0
+    # back to the plane's coordinates
+    off = P[0] - np.concatenate([pts[0], [0.0]]) @ R.T
+    g2 = (G - off) @ R
+    s2 = pts[interior[src]]
+    np.testing.assert_allclose(g2[:, 0], -s2[:, 0], atol=1e-12)
+    np.testing.assert_allclose(g2[:, 1], s2[:, 1], atol=1e-12)
+    np.testing.assert_allclose(g2[:, 2], 0.0, atol=1e-12)
+    # every ghost's source had a boundary point among its K nearest neighbours
+    nbr, _ = oracle_mod.knn(P, 16)
+    assert mask[nbr[interior[src]]].any(1).all()
+
+
+def test_neumann_rows_sum_to_zero_and_converge(oracle_mod):
+    """Folded rows still sum to zero (constants are in the kernel of the Neumann Laplacian), and
+    on the upper hemisphere (sigma - Delta) U = (sigma + 6) z^2 - 2 with dU/dn = 0 at the equator
+    has the solution U = z^2: the discrete solution approaches it."""
+    errs = []
+    for n in (2000, 8000):
+        cl = clouds.hemisphere(n, 8, 20)
+        P, m = cl.points, cl.meta["boundary"]
+        rp, c, v, g = oracle_mod.neumann_rows(P, m, 20, 6)
+        rs = np.add.reduceat(v, rp[:-1])
+        assert np.abs(rs).max() <= 1e-12 * np.abs(v).max() * 20
+        z = P[g[0], 2]
+        x = oracle_mod.solve(rp, c, v, 7.0 * z ** 2 - 2.0, sigma=1.0)
+        errs.append(np.abs(x - z ** 2).max())
+    assert errs[0] < 5e-3 and errs[0] / errs[1] > 3.0, errs
