@@ -271,6 +271,48 @@ typedef struct {
 mvgd_status mvgd_solve(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_params *p,
                        mvgd_solve_info *info, void *stream);
 
+/*
+ * mvgd_assemble_neumann -- L for an open surface in R^3 with the homogeneous Neumann condition,
+ * imposed by reflection (Sec. 3.1).
+ *
+ * The cloud is split into interior points P^I (boundary[i] == 0) and boundary points P^B. An
+ * interior point that has a boundary point among its K nearest neighbours (in the whole cloud)
+ * gets a ghost point: its mirror image across the boundary, p^R = p - 2 ((p - p^B) . e3) e3, with
+ * p^B its closest boundary point (ties to the smaller index) and e3 = e1 x e2 / |e1 x e2| there;
+ * e1 is the tangent at p^B of the boundary curve, fitted by quadratic least squares (in the PCA
+ * frame of the k_boundary nearest boundary points, p^B included) and e2 the surface normal (the
+ * smallest-eigenvalue eigenvector of the covariance of the K nearest points of the whole cloud).
+ * All of this is computed in double. MVGD rows (mvgd_assemble) are then built on the augmented
+ * cloud P^I u P^R, and every ghost column is folded into its source's column (a zero normal
+ * derivative gives the ghost its source's value). Boundary points carry no row.
+ *
+ * Rows of the returned handle: [0, n_interior) the interior points, in ascending order of their
+ * index in `points`; [n_interior, n_interior + n_ghost) the ghosts, whose rows are zero (fix them
+ * in mvgd_solve, or solve with sigma != 0). Interior rows reference interior columns only; a
+ * column that a fold duplicates is merged into one entry, which leaves a zero entry whose column
+ * is the row itself.
+ *
+ * points      device, [n_total, 3], float (MVGD_FP32_MIXED) or double (MVGD_FP64). One cloud.
+ * boundary    device, uint8 [n_total], nonzero = boundary point.
+ * k_boundary  boundary points in the curve fit, 3..16 (at most the number of boundary points).
+ * p           as for mvgd_assemble, with n_ambient = 3 and d_manifold = 2.
+ * ghost_xyz   device double [n_total * 3] or NULL: the ghost points in FP64, row-major, ghost g at
+ *             [3g, 3g + 3) (g = its row - n_interior).
+ * ghost_src   device int32 [n_total]: the source of ghost g as an interior row.
+ * info        host: n_interior and n_ghost.
+ * The call waits for `stream` twice (the assembly's own wait, and once to size the ghost set).
+ * MVGD_EINVAL when there are fewer boundary points than k_boundary or at most k interior points.
+ */
+typedef struct {
+    int64_t n_interior;
+    int64_t n_ghost;
+} mvgd_neumann_info;
+
+mvgd_status mvgd_assemble_neumann(const void *points, int64_t n_total, const uint8_t *boundary,
+                                  int32_t k_boundary, const mvgd_params *p, void *stream,
+                                  mvgd_matrix **out, double *ghost_xyz, int32_t *ghost_src,
+                                  mvgd_neumann_info *info);
+
 /* mvgd_pool_trim -- device memory of the current device that the library keeps cached. Handles
  * and assembly scratch come from a stream-ordered pool owned by the library, one per device; freed
  * memory stays in the pool for later calls (no fresh mapping per assembly). This call returns the

@@ -18,6 +18,7 @@
 #include "apply.hpp"
 #include "assemble.hpp"
 #include "bin.hpp"
+#include "boundary.hpp"
 #include "common.hpp"
 #include "solve.hpp"
 #include "stats.hpp"
@@ -646,9 +647,176 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
     return MVGD_OK;
 }
 
+// Exclusive prefix sum of n uint32 into out[0..n] (out[n] = total), stream-ordered; the level
+// buffers come from one pool allocation freed stream-ordered.
+mvgd_status scan_u32(const uint32_t *in, uint32_t *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) {
+        scan_total_kernel<<<1, 64, 0, s>>>(in, out, 0);
+        return check_launch("scan");
+    }
+    std::vector<int64_t> lvl_n;
+    for (int64_t m = n; m > 1; m = (m + kScanTile - 1) / kScanTile)
+        lvl_n.push_back(m);
+    if (lvl_n.empty())
+        lvl_n.push_back(n);
+    std::vector<uint32_t *> lvl_sum(lvl_n.size()), lvl_off(lvl_n.size());
+    auto carve = [&](Carver &cv) {
+        for (size_t l = 0; l < lvl_n.size(); ++l) {
+            const int64_t tiles = (lvl_n[l] + kScanTile - 1) / kScanTile;
+            cv.take(lvl_sum[l], sizeof(uint32_t) * tiles);
+            cv.take(lvl_off[l], sizeof(uint32_t) * tiles);
+        }
+    };
+    Carver sz;
+    carve(sz);
+    void *work = nullptr;
+    if (dev_alloc(&work, sz.off, s) != hipSuccess)
+        return fail(MVGD_ENOMEM, "device allocation failed (scan, %zu bytes)", sz.off);
+    Carver cv{(char *)work, 0};
+    carve(cv);
+    const uint32_t *src = in;
+    uint32_t *o = out;
+    for (size_t l = 0; l < lvl_n.size(); ++l) {
+        const int64_t tiles = (lvl_n[l] + kScanTile - 1) / kScanTile;
+        scan_tile_kernel<<<(unsigned)tiles, kScanThreads, 0, s>>>(src, o, lvl_sum[l], lvl_n[l]);
+        src = lvl_sum[l];
+        o = lvl_off[l];
+    }
+    for (size_t l = lvl_n.size(); l-- > 1;) {
+        uint32_t *dst = (l - 1 == 0) ? out : lvl_off[l - 2];
+        scan_add_kernel<<<(unsigned)((lvl_n[l - 1] + kScanTile - 1) / kScanTile), kScanThreads, 0,
+                          s>>>(dst, lvl_off[l - 1], lvl_n[l - 1]);
+    }
+    scan_total_kernel<<<1, 64, 0, s>>>(in, out, n);
+    (void)hipFreeAsync(work, s);
+    return check_launch("scan");
+}
+
+template <typename T>
+mvgd_status neumann_impl(const T *points, int64_t n, const uint8_t *boundary, int kb,
+                         const mvgd_params &p, hipStream_t s, mvgd_matrix **out,
+                         double *ghost_xyz, int32_t *ghost_src, mvgd_neumann_info *info)
+{
+    const int K = p.k;
+    const std::vector<int64_t> whole = {0, n};
+    mvgd_matrix *H0 = nullptr;
+    if (mvgd_status st = assemble_impl<T>(points, n, whole, p, s, &H0); st != MVGD_OK)
+        return st;
+    struct Free0 {
+        mvgd_matrix *&h;
+        ~Free0() { if (h) release(h); }
+    } free0{H0};
+    // work: flags and their prefix sums, lists, inverse permutation, frames, augmented cloud
+    uint32_t *flag, *isi, *isb, *rf, *ri, *rb;
+    int32_t *fl, *il, *bl, *ipos0, *ipos1;
+    double *e3;
+    T *aug;
+    auto carve = [&](Carver &cv) {
+        for (uint32_t **v : {&flag, &isi, &isb})
+            cv.take(*v, sizeof(uint32_t) * (size_t)n);
+        for (uint32_t **v : {&rf, &ri, &rb})
+            cv.take(*v, sizeof(uint32_t) * (size_t)(n + 1));
+        for (int32_t **v : {&fl, &il, &bl, &ipos0})
+            cv.take(*v, sizeof(int32_t) * (size_t)n);
+        cv.take(ipos1, sizeof(int32_t) * (size_t)(2 * n)); // the augmented cloud: n_i + n_f <= 2n
+        cv.take(e3, sizeof(double) * 3 * (size_t)n);
+        cv.take(aug, sizeof(T) * 3 * (size_t)(2 * n));
+    };
+    Carver sz;
+    carve(sz);
+    void *work = nullptr;
+    if (dev_alloc(&work, sz.off, s) != hipSuccess)
+        return fail(MVGD_ENOMEM, "device allocation failed (Neumann work, %zu bytes)", sz.off);
+    struct FreeW {
+        void *w;
+        hipStream_t s;
+        ~FreeW() { (void)hipFreeAsync(w, s); }
+    } freew{work, s};
+    Carver cv{(char *)work, 0};
+    carve(cv);
+    const unsigned nb256 = (unsigned)((n + 255) / 256);
+    nm_flag_kernel<<<nb256, 256, 0, s>>>(H0->ell_col, H0->perm, boundary, n, H0->ld, K, flag, isi,
+                                         isb);
+    for (auto pr : {std::make_pair(isi, ri), std::make_pair(isb, rb), std::make_pair(flag, rf)})
+        if (mvgd_status st = scan_u32(pr.first, pr.second, n, s); st != MVGD_OK)
+            return st;
+    nm_compact_kernel<<<nb256, 256, 0, s>>>(isi, ri, n, il);
+    nm_compact_kernel<<<nb256, 256, 0, s>>>(isb, rb, n, bl);
+    nm_compact_kernel<<<nb256, 256, 0, s>>>(flag, rf, n, fl);
+    nm_inverse_kernel<<<nb256, 256, 0, s>>>(H0->perm, n, ipos0);
+    uint32_t tot[3] = {0, 0, 0};
+    if (hipMemcpyAsync(&tot[0], ri + n, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&tot[1], rb + n, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&tot[2], rf + n, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MVGD_EDEVICE, "reading the boundary counts failed");
+    const int64_t ni = tot[0], nbd = tot[1], nf = tot[2];
+    if (nbd < kb)
+        return fail(MVGD_EINVAL, "%lld boundary points; k_boundary = %d needs at least as many",
+                    (long long)nbd, kb);
+    if (ni < K + 1)
+        return fail(MVGD_EINVAL, "%lld interior points; needs more than k = %d", (long long)ni, K);
+    if (nbd > 0)
+        nm_frame_kernel<T><<<(unsigned)((nbd + 63) / 64), 64, 0, s>>>(
+            points, bl, nbd, kb, H0->ell_col, H0->perm, ipos0, H0->ld, K, e3);
+    nm_gather_kernel<T><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(points, il, ni, aug);
+    if (nf > 0)
+        nm_ghost_kernel<T><<<(unsigned)((nf + 255) / 256), 256, 0, s>>>(
+            points, fl, nf, bl, nbd, e3, ri, ni, aug, ghost_src, ghost_xyz);
+    if (mvgd_status st = check_launch("ghost points"); st != MVGD_OK)
+        return st;
+    const std::vector<int64_t> whole_aug = {0, ni + nf};
+    mvgd_matrix *H = nullptr;
+    if (mvgd_status st = assemble_impl<T>(aug, ni + nf, whole_aug, p, s, &H); st != MVGD_OK)
+        return st;
+    // fold, through the inverse permutation of the augmented assembly
+    nm_inverse_kernel<<<(unsigned)((ni + nf + 255) / 256), 256, 0, s>>>(H->perm, ni + nf, ipos1);
+    nm_fold_kernel<T><<<(unsigned)((ni + nf + 255) / 256), 256, 0, s>>>(
+        H->ell_col, (T *)H->ell_val, H->perm, ipos1, ghost_src, ni + nf, H->ld, K + 1, ni);
+    if (mvgd_status st = check_launch("fold"); st != MVGD_OK) {
+        release(H);
+        return st;
+    }
+    info->n_interior = ni;
+    info->n_ghost = nf;
+    *out = H;
+    return MVGD_OK;
+}
+
 } // namespace
 
 extern "C" {
+
+mvgd_status mvgd_assemble_neumann(const void *points, int64_t n_total, const uint8_t *boundary,
+                                  int32_t k_boundary, const mvgd_params *p, void *stream,
+                                  mvgd_matrix **out, double *ghost_xyz, int32_t *ghost_src,
+                                  mvgd_neumann_info *info)
+{
+    std::vector<int64_t> offs;
+    mvgd_status st = validate(points, n_total, nullptr, 1, p, out, offs);
+    if (st != MVGD_OK)
+        return st;
+    if (!boundary || !ghost_src || !info)
+        return fail(MVGD_EINVAL, "boundary, ghost_src or info is NULL");
+    if (p->n_ambient != 3 || p->d_manifold != 2)
+        return fail(MVGD_EUNSUPPORTED, "the Neumann condition is built for surfaces in R^3");
+    if (k_boundary < 3 || k_boundary > 16)
+        return fail(MVGD_EINVAL, "k_boundary must be in [3, 16] (got %d)", k_boundary);
+    memset(info, 0, sizeof *info);
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess)
+        return fail(MVGD_EDEVICE, "no HIP device");
+    if (!is_device_pointer(boundary, device) || !is_device_pointer(ghost_src, device) ||
+        (ghost_xyz && !is_device_pointer(ghost_xyz, device)))
+        return fail(MVGD_EINVAL, "boundary, ghost_src and ghost_xyz must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    if (p->precision == MVGD_FP64)
+        return neumann_impl<double>((const double *)points, n_total, boundary, k_boundary, *p, s,
+                                    out, ghost_xyz, ghost_src, info);
+    return neumann_impl<float>((const float *)points, n_total, boundary, k_boundary, *p, s, out,
+                               ghost_xyz, ghost_src, info);
+}
 
 mvgd_status mvgd_assemble(const void *points, int64_t n_total, const int64_t *cloud_offsets,
                           int32_t n_clouds, const mvgd_params *p, void *stream, mvgd_matrix **out)

@@ -25,7 +25,8 @@ MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 
 MVGD_FLAG_MLS, MVGD_FLAG_DIVERGENCE = 16, 32
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
-           "mvgd_timing", "mvgd_row_stats", "mvgd_solve", "mvgd_pool_trim", "mvgd_status_str",
+           "mvgd_timing", "mvgd_row_stats", "mvgd_solve", "mvgd_assemble_neumann",
+           "mvgd_pool_trim", "mvgd_status_str",
            "mvgd_last_error", "mvgd_version")
 
 
@@ -80,6 +81,10 @@ class mvgd_solve_params(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("fixed", ctypes.c_void_p)]
 
 
+class mvgd_neumann_info(ctypes.Structure):
+    _fields_ = [("n_interior", ctypes.c_int64), ("n_ghost", ctypes.c_int64)]
+
+
 class mvgd_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double)]
@@ -111,6 +116,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mvgd_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mvgd_solve_params),
                                ctypes.POINTER(mvgd_solve_info), vp]
     lib.mvgd_solve.restype = i32
+    lib.mvgd_assemble_neumann.argtypes = [vp, i64, vp, i32, ctypes.POINTER(mvgd_params), vp,
+                                          ctypes.POINTER(vp), vp, vp,
+                                          ctypes.POINTER(mvgd_neumann_info)]
+    lib.mvgd_assemble_neumann.restype = i32
     lib.mvgd_pool_trim.argtypes = [ctypes.c_size_t]
     lib.mvgd_pool_trim.restype = i32
     lib.mvgd_status_str.argtypes = [i32]
@@ -161,14 +170,7 @@ class Matrix:
             pass
 
 
-def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision=None,
-                  flags: int = 0, h_override: float | None = None, d_manifold: int = 2,
-                  tuning: dict | None = None, stream=None) -> Matrix:
-    """Assemble L from device points [N, n] (float32 -> FP32-mixed, float64 -> FP64).
-
-    tuning: neighbour-search tunables {cell_alpha, radius_mu, cells_per_point, launch}; by
-    default the autotuner's table (tuning.json) is consulted for this shape.
-    """
+def _params(points, k, precision, flags, h_override, d_manifold, tuning, n_per_cloud):
     if not isinstance(points, torch.Tensor) or points.dim() != 2:
         raise ValueError("points must be a 2-D torch tensor")
     if precision is None:
@@ -183,15 +185,26 @@ def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision
         flags |= MVGD_FLAG_H_OVERRIDE
     if tuning is None:
         from . import autotune
-        tuning = autotune.lookup(points.shape[1], k, precision,
-                                 points.shape[0] if cloud_offsets is None
-                                 else points.shape[0] // max(1, len(cloud_offsets) - 1),
-                                 d_manifold)
+        tuning = autotune.lookup(points.shape[1], k, precision, n_per_cloud, d_manifold)
     t = tuning or {}
     p = mvgd_params(points.shape[1], d_manifold, k, prec, flags, float(h_override or 0.0),
                     float(t.get("cell_alpha", 0.0)), float(t.get("radius_mu", 0.0)),
                     float(t.get("cells_per_point", 0.0)), int(t.get("launch", 0)),
                     int(t.get("search", 0)))
+    return p, want
+
+
+def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision=None,
+                  flags: int = 0, h_override: float | None = None, d_manifold: int = 2,
+                  tuning: dict | None = None, stream=None) -> Matrix:
+    """Assemble L from device points [N, n] (float32 -> FP32-mixed, float64 -> FP64).
+
+    tuning: neighbour-search tunables {cell_alpha, radius_mu, cells_per_point, launch}; by
+    default the autotuner's table (tuning.json) is consulted for this shape.
+    """
+    n_per = (points.shape[0] if cloud_offsets is None
+             else points.shape[0] // max(1, len(cloud_offsets) - 1))
+    p, want = _params(points, k, precision, flags, h_override, d_manifold, tuning, n_per)
     offs_ptr, n_clouds = None, 1
     if cloud_offsets is not None:
         offs = (ctypes.c_int64 * len(cloud_offsets))(*[int(v) for v in cloud_offsets])
@@ -201,6 +214,35 @@ def mvgd_assemble(points: torch.Tensor, k: int, *, cloud_offsets=None, precision
                               n_clouds, ctypes.byref(p), ctypes.c_void_p(_stream(stream)),
                               ctypes.byref(out)))
     return Matrix(out.value, points.shape[0], k, want, points.device)
+
+
+def mvgd_assemble_neumann(points: torch.Tensor, boundary: torch.Tensor, k: int,
+                          k_boundary: int = 8, *, precision=None, flags: int = 0,
+                          h_override: float | None = None, tuning: dict | None = None,
+                          stream=None):
+    """L on an open surface in R^3 with the homogeneous Neumann condition by reflection.
+
+    points [N, 3] (device), boundary [N] (device bool or uint8, nonzero = boundary point).
+    Returns (L, n_interior, ghost_xyz [n_ghost, 3] float64, ghost_src [n_ghost] int32): rows
+    [0, n_interior) of L are the interior points in ascending index order, the rest are the
+    ghosts' zero rows.
+    """
+    p, want = _params(points, k, precision, flags, h_override, 2, tuning, points.shape[0])
+    if boundary.shape != (points.shape[0],):
+        raise ValueError("boundary must have one entry per point")
+    b = boundary.to(torch.uint8).contiguous()
+    n = points.shape[0]
+    gx = torch.empty((n, 3), dtype=torch.float64, device=points.device)
+    gs = torch.empty((n,), dtype=torch.int32, device=points.device)
+    out, info = ctypes.c_void_p(), mvgd_neumann_info()
+    _check(_lib.mvgd_assemble_neumann(ctypes.c_void_p(points.data_ptr()), n,
+                                      ctypes.c_void_p(b.data_ptr()), int(k_boundary),
+                                      ctypes.byref(p), ctypes.c_void_p(_stream(stream)),
+                                      ctypes.byref(out), ctypes.c_void_p(gx.data_ptr()),
+                                      ctypes.c_void_p(gs.data_ptr()), ctypes.byref(info)))
+    ni, ng = int(info.n_interior), int(info.n_ghost)
+    L = Matrix(out.value, ni + ng, k, want, points.device)
+    return L, ni, gx[:ng], gs[:ng]
 
 
 def mvgd_apply(L: Matrix, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):

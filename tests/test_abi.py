@@ -110,3 +110,26 @@ def test_apply_and_free_accept_null_safely(mv):
     prm, info = mv.mvgd_solve_params(0, 10, 1e-8, 0.0, 0.0, 0, 0, None), mv.mvgd_solve_info()
     assert lib.mvgd_solve(None, None, None, ctypes.byref(prm), ctypes.byref(info), None) == -1
     lib.mvgd_free(None)
+
+
+def test_neumann_arguments_rejected_on_host(mv):
+    lib = mv._lib
+    fake = ctypes.c_void_p(0x2000)
+
+    def call(p, kb=8, boundary=fake, src=fake, info=True):
+        o, inf = ctypes.c_void_p(), mv.mvgd_neumann_info()
+        st = lib.mvgd_assemble_neumann(ctypes.c_void_p(0x1000), 1000, boundary, kb,
+                                       ctypes.byref(p), None, ctypes.byref(o), None, src,
+                                       ctypes.byref(inf) if info else None)
+        assert o.value is None
+        return st
+
+    p3 = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, 0, 0.0)
+    assert call(p3, boundary=None) == mv.MVGD_EINVAL
+    assert call(p3, src=None) == mv.MVGD_EINVAL
+    assert call(p3, info=False) == mv.MVGD_EINVAL
+    assert call(p3, kb=2) == mv.MVGD_EINVAL
+    assert call(p3, kb=17) == mv.MVGD_EINVAL
+    assert call(mv.mvgd_params(4, 2, 20, mv.MVGD_FP64, 0, 0.0)) == mv.MVGD_EUNSUPPORTED
+    assert call(mv.mvgd_params(3, 1, 6, mv.MVGD_FP64, 0, 0.0)) == mv.MVGD_EUNSUPPORTED
+    assert call(mv.mvgd_params(3, 2, 4, mv.MVGD_FP64, 0, 0.0)) == mv.MVGD_EINVAL  # k too small

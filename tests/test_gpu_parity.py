@@ -739,3 +739,108 @@ def test_serving_admission_with_tiny_budget():
     st = serve.Server(precision="fp32", n_streams=4, max_batch=8, hbm_budget_bytes=budget).run(reqs)
     assert st.summary()["requests"] == len(reqs)
     assert st.admission_waits > 0 and max(st.batch_sizes) == 1
+
+
+# ----------------------------------------------------------------------------------------------
+# Neumann condition by reflection (Sec. 3.1)
+# ----------------------------------------------------------------------------------------------
+def _neumann_case(mv, n, precision, k=20, kb=6, seed=8):
+    cl = clouds.hemisphere(n, seed, k)
+    m = cl.meta["boundary"]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    P = torch.tensor(cl.points, dtype=dt, device=DEV)
+    L, ni, gx, gs = mv.mvgd_assemble_neumann(P, torch.tensor(m, device=DEV), k, kb)
+    torch.cuda.synchronize()
+    pts = _oracle_points(cl.points, precision)
+    interior, G, src, _ = oracle.neumann_ghosts(pts, m, k, kb)
+    gxyz, gsrc = gx.cpu().numpy(), gs.cpu().numpy().astype(np.int64)
+    return cl, m, pts, L, ni, gxyz, gsrc, interior, G, src
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [4000, 20000])
+def test_neumann_ghosts_and_rows(mv, precision, n):
+    """Ghost set (which interior points get one, and their order) exactly as the oracle's; ghost
+    coordinates (FP64 on both sides, from the same coordinates) to 1e-10; the folded interior rows
+    against the oracle's rows on the GPU's ghosts to the row bar (twice the per-row tolerance: a
+    folded entry is the sum of two), ghost rows zero, no ghost column left."""
+    k, kb = 20, 6
+    cl, m, pts, L, ni, gxyz, gsrc, interior, G, src = _neumann_case(mv, n, precision, k, kb)
+    assert ni == len(interior)
+    assert gsrc.shape == src.shape and (gsrc == src).all()
+    gerr = np.abs(gxyz - G).max()
+    assert gerr <= 1e-10, gerr
+    ng = len(gsrc)
+    # the oracle on the ghosts the GPU assembled on (rounded to the matrix dtype, as in its cloud)
+    Gg = gxyz if precision == "fp64" else gxyz.astype(np.float32).astype(np.float64)
+    A = np.concatenate([pts[interior], Gg])
+    o_cols, o_vals, dg = oracle.rows(A, k, rows=np.arange(ni), diag=True)
+    tol = 2.0 * _row_tol(precision, dg, _kappa(A, np.arange(ni), o_cols, dg))
+    orp, oc, ov, _ = oracle.neumann_rows(pts, m, k, kb, ghosts=(interior, Gg, gsrc, None))
+    rp, c, v = _export_csr(mv, L, ni + ng, k)
+    assert (np.abs(v[rp[ni]:]) == 0).all(), "ghost rows must be zero"
+    live = v[:rp[ni]] != 0
+    assert (c[:rp[ni]][live] < ni).all(), "an interior row still references a ghost"
+    import scipy.sparse as sp
+    Ag = sp.csr_matrix((v[:rp[ni]], c[:rp[ni]], rp[:ni + 1]), shape=(ni, ni + ng))[:, :ni]
+    Ao = sp.csr_matrix((ov, oc, orp), shape=(ni, ni))
+    D = (Ag - Ao).tocsr()
+    err = np.zeros(ni)
+    np.maximum.at(err, np.repeat(np.arange(ni), np.diff(D.indptr)), np.abs(D.data))
+    rel = err / np.abs(o_vals).max(1)
+    bad = np.nonzero(rel > tol)[0]
+    assert bad.size == 0, f"{bad.size} rows over tolerance, worst {rel.max():.3e} at {bad[:5]}"
+    # every distinct column once: no duplicate nonzero (row, column) pair in the export
+    rows = np.repeat(np.arange(ni), np.diff(rp[:ni + 1]))
+    key = rows[live] * (ni + ng) + c[:rp[ni]][live]
+    assert len(np.unique(key)) == len(key)
+    # rows sum to zero: constants are in the kernel of the Neumann Laplacian
+    rs = np.asarray(Ag.sum(1)).ravel()
+    assert np.abs(rs).max() <= (1e-10 if precision == "fp64" else 1e-3) * np.abs(o_vals).max()
+    print(f"\n[neumann hemisphere N={cl.n_points} {precision}] interior {ni}, ghosts {ng}, "
+          f"max ghost err {gerr:.2e}, max row rel err {rel.max():.2e}")
+    L.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_neumann_hemisphere_solve(mv, precision):
+    """(sigma - Delta) U = (sigma + 6) z^2 - 2 on the upper hemisphere with dU/dn = 0 on the
+    equator (solution U = z^2), sigma = 1: BiCGSTAB on the Neumann handle (ghost rows zero, so
+    their unknowns solve sigma x = 0) matches the sparse-LU solution of the exported matrix and
+    approaches z^2."""
+    cl = clouds.hemisphere(4000, 8, 20)
+    m = cl.meta["boundary"]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    P = torch.tensor(cl.points, dtype=dt, device=DEV)
+    L, ni, gx, gs = mv.mvgd_assemble_neumann(P, torch.tensor(m, device=DEV), 20, 6)
+    ng = gs.shape[0]
+    pts = _oracle_points(cl.points, precision)
+    z = pts[~m, 2]
+    b = np.concatenate([7.0 * z ** 2 - 2.0, np.zeros(ng)])
+    rtol = 1e-12 if precision == "fp64" else 1e-6
+    x, info = mv.mvgd_solve(L, torch.tensor(b, dtype=dt, device=DEV), sigma=1.0, rtol=rtol,
+                            max_iter=4000)
+    assert info["converged"] == 1, info
+    got = x.cpu().numpy().astype(np.float64)
+    assert (got[ni:] == 0).all()
+    rp, c, v = _export_csr(mv, L, ni + ng, 20)
+    ref = oracle.solve(rp, c, v, b, sigma=1.0)
+    kappa = _cond_bound(rp, c, v, 1.0, [])
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    store = 0.0 if precision == "fp64" else 2.0 ** -24
+    assert rel <= 10 * kappa * info["rel_residual"] + 4 * store, (rel, kappa, info)
+    err = np.abs(got[:ni] - cl.points[~m, 2] ** 2).max()
+    assert err < 2e-3, err
+    print(f"\n[neumann hemisphere solve 4k {precision}] {info}, kappa {kappa:.2e}, rel err vs LU {rel:.2e}, "
+          f"max|x - z^2| {err:.2e}")
+    L.free()
+
+
+def test_neumann_rejects_too_few_boundary_points(mv):
+    """k_boundary larger than the number of boundary points is an argument error, and leaves no
+    handle."""
+    cl = clouds.hemisphere(2000, 8, 20, n_boundary=5)
+    P = torch.tensor(cl.points, device=DEV)
+    with pytest.raises(mv.MvgdError) as e:
+        mv.mvgd_assemble_neumann(P, torch.tensor(cl.meta["boundary"], device=DEV), 20, 6)
+    assert e.value.status == mv.MVGD_EINVAL
