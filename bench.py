@@ -206,6 +206,71 @@ def bench_solve(args):
     print(json.dumps(out))
 
 
+def bench_neumann(args):
+    """Open surface with the Neumann condition (Sec. 3.1): upper unit hemisphere, N interior points
+    plus ~sqrt(pi N) equispaced points on the boundary circle, K = 20. A step is one
+    mvgd_assemble_neumann (search on the whole cloud, boundary frames, ghost points, assembly on
+    the augmented cloud, folding), timed by wall clock around each call (the call itself waits
+    for the stream); the plain assembly of the same cloud is timed alongside. Then
+    (sigma - Delta) U = (sigma + 6) z^2 - 2, sigma = 1, with dU/dn = 0 (solution z^2) by BiCGSTAB on
+    the device. Prints one JSON line."""
+    import torch
+    from paper_1603_04100_amd import clouds, mvgd as mv
+    n, k, kb = args.solve_points, 20, 6
+    cl = clouds.hemisphere(n, 8, k)
+    m = cl.meta["boundary"]
+    dev = "cuda:0"
+    print(f"[bench] hemisphere Neumann: N={cl.n_points} K={k} boundary {int(m.sum())}",
+          file=sys.stderr, flush=True)
+    res = {}
+    bmask = torch.tensor(m, device=dev)
+    for prec, dt, rtol in (("fp32", torch.float32, 1e-6), ("fp64", torch.float64, 1e-10)):
+        P = torch.tensor(cl.points, dtype=dt, device=dev)
+        for _ in range(max(1, args.warmup)):
+            L, ni, gx, gs = mv.mvgd_assemble_neumann(P, bmask, k, kb)
+            mv.mvgd_free(L)
+            mv.mvgd_free(mv.mvgd_assemble(P, k))
+        torch.cuda.synchronize()
+        tn, tp = [], []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            L, ni, gx, gs = mv.mvgd_assemble_neumann(P, bmask, k, kb)
+            torch.cuda.synchronize()
+            tn.append(time.perf_counter() - t0)
+            if _ < args.steps - 1:
+                mv.mvgd_free(L)
+            t0 = time.perf_counter()
+            Lp = mv.mvgd_assemble(P, k)
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+            mv.mvgd_free(Lp)
+        ng = int(gs.shape[0])
+        z = cl.points[~m, 2]
+        b = torch.tensor(np.concatenate([7.0 * z ** 2 - 2.0, np.zeros(ng)]), dtype=dt, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = mv.mvgd_solve(L, b, sigma=1.0, rtol=rtol, max_iter=40000, check_every=50)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        err = float((x[:ni].double().cpu() - torch.tensor(z ** 2)).abs().max())
+        mv.mvgd_free(L)
+        med_n, med_p = float(np.median(tn)), float(np.median(tp))
+        res[prec] = {"assemble_neumann_ms": med_n * 1e3, "assemble_plain_ms": med_p * 1e3,
+                     "rows_per_s": ni / med_n, "n_interior": ni, "n_ghost": ng,
+                     "solve": info, "solve_s": ts, "max_abs_err_vs_z2": err}
+        print(f"[bench] {prec}: {res[prec]}", file=sys.stderr, flush=True)
+    out = {"metric": "MVGD rows/s with the Neumann condition by reflection (open surface)",
+           "value": res["fp32"]["rows_per_s"], "unit": "rows/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["fp32"]["assemble_neumann_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 storage/f64 solves",
+           "data": "synthetic", "config": {"workload": "hemisphere_neumann",
+                                           "n_points": cl.n_points, "k": k, "k_boundary": kb,
+                                           "sigma": 1.0},
+           "results": res, "kernel_source_hash": kernel_source_hash()}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +300,8 @@ def main():
         return bench_serving(args)
     if args.workload == "sphere_poisson":
         return bench_solve(args)
+    if args.workload == "hemisphere_neumann":
+        return bench_neumann(args)
     cl = make_workload(args.workload)
     n, k = cl.n_points, cl.k
     batched = cl.offsets.shape[0] > 2

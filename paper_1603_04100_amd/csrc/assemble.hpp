@@ -68,13 +68,22 @@ constexpr int kLdsBndPos = kLdsHist + kBndCap * kWave * 8;  // i32 [kBndCap][64]
 constexpr int kLdsSearch = kLdsBndPos + kBndCap * kWave * 4; // group search staging
 static_assert(kBinWords * kWave * 4 <= kBndCap * kWave * 8, "histogram must fit the key area");
 
-// LDS of one search wave: histogram / boundary keys and indices, plus (group search) the cell
-// ranges, the staged points and the sub-group worklist
-__host__ __device__ constexpr int search_lds_bytes(int pt_bytes, bool group)
+// Staging of one group / tile stream (S = 0: coordinates of 64 points, their sorted positions
+// and original indices; S = 2: the 64 candidates' six augmented operands, positions, indices).
+constexpr int kTileStage = 6 * kWave * 4 + 2 * kWave * 4;
+__host__ __device__ constexpr int search_stage_bytes(int pt_bytes, int S)
 {
-    return kLdsSearch + (group ? 2 * kWave * 4 /*cell ranges*/ + kWave * pt_bytes +
-                                     2 * kWave * 4 /*staged pos, idx*/ + kWave * 8 /*worklist*/
-                               : 0);
+    return S == 2 ? kTileStage : kWave * pt_bytes + 2 * kWave * 4;
+}
+
+// LDS of one search wave (S: 0 group, 1 lane, 2 tile): histogram / boundary keys and indices,
+// plus (group and tile search) the cell ranges, the staging, the sub-group worklist and (tile)
+// the per-query sure / boundary counters
+__host__ __device__ constexpr int search_lds_bytes(int pt_bytes, int S)
+{
+    return kLdsSearch + (S == 1 ? 0
+                                : 2 * kWave * 4 /*cell ranges*/ + search_stage_bytes(pt_bytes, S) +
+                                      kWave * 8 /*worklist*/ + (S == 2 ? 2 * kWave * 4 : 0));
 }
 
 // LDS of one fit wave: the neighbour list [K][64]
@@ -223,6 +232,140 @@ __device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g
         }
     }
     return streamed;
+}
+
+// ---------------------------------------------------------------------------------------------
+// tile search (float points): squared distances of a 64-query x 64-candidate tile on the
+// matrix cores
+// ---------------------------------------------------------------------------------------------
+// About a centre c (a query of the sub-group), with q^ = q - c and p^ = p - c rounded to FP32,
+//   g(q, p) = |q^|^2 + (1 + kTileAdd) |p^|^2 - 2 q^ . p^
+// is one dot product of the augmented vectors (-2 q^, 1, |q^|^2) and (p^, (1 + kTileAdd)|p^|^2, 1),
+// six terms, formed by three v_mfma_f32_32x32x2f32 per 32 x 32 block. Its error against the
+// exact key (FP64, no contraction) obeys |f - key| <= e key + kTileErr (|p^|^2 + |q^|^2) for the
+// plain value f (FP32 rounding of the centring, the norms and the six-term sum: below 20 u with
+// u = 2^-24); kTileErr = 4e-6 leaves a factor three. The extra kTileAdd |p^|^2 makes g an
+// upper-biased estimate whose bounds involve |q^|^2 only:
+//   key <= (g + kTileErr |q^|^2) / (1 - e),
+//   g   <= key (1 + e + 2 c) + (kTileErr + 2 c) |q^|^2,  c = kTileErr + kTileAdd + u,
+// the second from |p^|^2 <= 2 |q^|^2 + 2 key. The selection thresholds below follow from these.
+constexpr float kTileErr = 4e-6f;
+constexpr float kTileAdd = 8e-6f;
+constexpr double kTilePeel = 100.0; // queries of one tile stream lie within sqrt(kTilePeel) r0 of c
+constexpr double kTileC = 4e-6 + 8e-6 + 6e-8;
+constexpr double kTileU1 = 1.0 + 4e-6 + 2.0 * kTileC; // key coefficient of the upper bound on g
+constexpr double kTileU0 = 4e-6 + 2.0 * kTileC;       // |q^|^2 coefficient of the upper bound on g
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// Stream every point of the cell box [bmin, bmax] of cloud g through LDS, 64 candidates at a
+// time, and call consume(cb, qb, acc) for each of the four 32 x 32 blocks of g(query, candidate):
+// in block (cb, qb) lane l holds query 32 qb + l % 32 against the candidates
+// 32 cb + 8 (r / 4) + 4 (l / 32) + r % 4 in acc[r], r = 0..15 (the accumulator layout of the
+// 32x32x2 instruction). bq[qb][s] are the query operands (augmented component 2 s + l / 32 of query
+// 32 qb + l % 32). Staged entries past the end of the stream get g = +inf (never selected: every
+// threshold is at most FLT_MAX) and original index 0x7fffffff.
+// Staged sorted positions and original indices are in st_pos / st_idx for the consumer.
+template <int NA, typename F>
+__device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &g, const int bmin[3],
+                                           const int bmax[3], char *lds_rng, char *lds_stage,
+                                           const float cq[4], const float (&bq)[2][3],
+                                           F &&consume)
+{
+    const int lane = lane_id();
+    const int hl = lane >> 5, ll = lane & 31;
+    const Pt<float> *spts = (const Pt<float> *)P.spts;
+    int32_t *rng_start = (int32_t *)lds_rng;
+    int32_t *rng_pref = rng_start + kWave;
+    float *st_aug = (float *)lds_stage;
+    int32_t *st_pos = (int32_t *)(lds_stage + 6 * kWave * 4);
+    int32_t *st_idx = st_pos + kWave;
+    const int nx = uniform(bmax[0] - bmin[0] + 1), ny = uniform(bmax[1] - bmin[1] + 1),
+              nz = uniform(bmax[2] - bmin[2] + 1);
+    const int bx0 = uniform(bmin[0]), by0 = uniform(bmin[1]), bz0 = uniform(bmin[2]);
+    const int nyz = ny * nz, ncells = nx * nyz;
+    int streamed = 0;
+    for (int cbase = 0; cbase < ncells; cbase += kWave) {
+        const int t = cbase + lane;
+        uint32_t st = 0, cn = 0;
+        if (t < ncells) {
+            const int x = (int)((uint32_t)t / (uint32_t)nyz);
+            const int r = t - x * nyz;
+            const int y = (int)((uint32_t)r / (uint32_t)nz);
+            const int z = r - y * nz;
+            const uint32_t cell = (uint32_t)g.cell0 + morton_of(P.parts, g, bx0 + x, by0 + y, bz0 + z);
+            st = P.cell_start[cell];
+            cn = P.cell_start[cell + 1] - st;
+        }
+        const int incl = wave_incl_scan((int)cn);
+        const int total = uniform(__shfl(incl, kWave - 1, kWave));
+        streamed += total;
+        rng_start[lane] = (int32_t)st;
+        rng_pref[lane] = incl - (int)cn;
+        __syncthreads();
+        for (int sb = 0; sb < total; sb += kWave) {
+            const int tt = sb + lane;
+            float av[6] = {0.f, 0.f, 0.f, 0.f, INFINITY, 1.f};
+            int32_t pos = -1, idx = 0x7fffffff;
+            if (tt < total) {
+                int lo = 0, hi = kWave - 1;
+                while (lo < hi) {
+                    int mid = (lo + hi + 1) >> 1;
+                    if (rng_pref[mid] <= tt)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                pos = rng_start[lo] + (tt - rng_pref[lo]);
+                const Pt<float> p = spts[pos];
+                float np = 0.f;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    av[a] = p.v[a] - cq[a];
+                    np = fmaf(av[a], av[a], np);
+                }
+                av[4] = np * (1.f + kTileAdd);
+                idx = P.perm[pos];
+            }
+#pragma unroll
+            for (int a = 0; a < 6; ++a)
+                st_aug[a * kWave + lane] = av[a];
+            st_pos[lane] = pos;
+            st_idx[lane] = idx;
+            __syncthreads();
+            const int nblk = (min(kWave, total - sb) + 31) >> 5;
+            for (int cb = 0; cb < nblk; ++cb) {
+                const float a0 = st_aug[hl * kWave + 32 * cb + ll];
+                const float a1 = st_aug[(2 + hl) * kWave + 32 * cb + ll];
+                const float a2 = st_aug[(4 + hl) * kWave + 32 * cb + ll];
+#pragma unroll
+                for (int qb = 0; qb < 2; ++qb) {
+                    floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                                    0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[qb][0], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[qb][1], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[qb][2], acc, 0, 0, 0);
+                    consume(cb, qb, acc);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    return streamed;
+}
+
+// float rounded towards -inf / +inf from a double (conservative thresholds); f32_up saturates at
+// FLT_MAX, so that a threshold never admits the +inf of a sentinel
+__device__ __forceinline__ float f32_down(double x)
+{
+    float f = (float)x;
+    return ((double)f > x) ? nextafterf(f, -INFINITY) : f;
+}
+__device__ __forceinline__ float f32_up(double x)
+{
+    float f = (float)x;
+    f = ((double)f < x) ? nextafterf(f, INFINITY) : f;
+    return fminf(f, 3.40282347e+38f);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1022,6 +1165,7 @@ __device__ __forceinline__ void search_lane(const AsmParams &P, const CloudGrid 
 template <typename T, int NA, int S>
 __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t group, char *lds)
 {
+    static_assert(S != 2 || sizeof(T) == 4, "the tile search is for float points");
     const int lane = lane_id();
     const int K = P.K;
     char *lds_rng = lds + kLdsSearch;
@@ -1084,12 +1228,16 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
         const uint32_t mc = morton_of(P.parts, g, cc[0], cc[1], cc[2]);
         const uint32_t mnext = __shfl_down(mc, 1, kWave);
         const int hb = (lane + 1 < cnt) ? (32 - (int)__clz((int)(mc ^ mnext))) : -1;
-        int2 *work = (int2 *)(lds_stage + kWave * sizeof(Pt<T>) + 2 * kWave * 4);
+        int2 *work = (int2 *)(lds_stage + search_stage_bytes((int)sizeof(Pt<T>), S));
         // Search box of a lane range for radius R: the range's bounding box in projected coordinates
         // grown by R (plus 1% of a cell, covering rounding in the binning), rounded out to cells.
         // Every point within distance R of a query of the range lies in it.
-        auto range_box = [&](int a, int b, double R, int lo_[3], int hi_[3]) {
-            const bool in = valid && lane >= a && lane < b;
+        // lanes of a range [a, b) that hold a query
+        auto lanes = [&](int a, int b) -> uint64_t {
+            return __ballot(valid && lane >= a && lane < b);
+        };
+        auto range_box = [&](uint64_t m, double R, int lo_[3], int hi_[3]) {
+            const bool in = (m >> lane) & 1ull;
             int cells = 1;
     #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
@@ -1115,14 +1263,14 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
             --top;
             const int ra = uniform(work[top].x), rb = uniform(work[top].y);
             int box_lo[3], box_hi[3];
-            const int cells = range_box(ra, rb, r0, box_lo, box_hi);
+            const int cells = range_box(lanes(ra, rb), r0, box_lo, box_hi);
             if (rb - ra >= 2 && cells > split_min) {
                 const int key = (lane >= ra && lane < rb - 1) ? hb * 64 + (63 - lane) : -1;
                 const int sk = uniform(seg_max(key, kWave));
                 const int sl = 63 - (sk & 63); // split after lane sl
                 int t0[3], t1[3];
-                const int c1 = range_box(ra, sl + 1, r0, t0, t1);
-                const int c2 = range_box(sl + 1, rb, r0, t0, t1);
+                const int c1 = range_box(lanes(ra, sl + 1), r0, t0, t1);
+                const int c2 = range_box(lanes(sl + 1, rb), r0, t0, t1);
                 if (c1 + c2 < cells) {
                     __syncthreads();
                     if (lane == 0) {
@@ -1134,196 +1282,466 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     continue;
                 }
             }
-            const bool act = valid && lane >= ra && lane < rb;
-            ++n_sub;
-            // ----- pass 1: histogram; grow the radius until every active lane counts K -----------
-            double R = r0;
-            float R2 = 0.f, s0b = 0.f;
-            int total = 0;
-            for (int grow = 0;; ++grow) {
-                if (grow > 0) {
-                    range_box(ra, rb, R, box_lo, box_hi);
-                    ++n_grow;
+            // Peels: for the tile search, the queries of the range within sqrt(kTilePeel) r0 of a
+            // centre query (the first one left), so that |q - c|^2 stays small against the search
+            // radius (the error of the tile distances grows with it); where a 2-D sheet crosses
+            // another in the binning projection, a range holds queries of both and is searched
+            // once per sheet. Other searches take the whole range at once.
+            const uint64_t whole = lanes(ra, rb);
+            uint64_t todo = whole;
+            while (todo != 0) {
+                uint64_t peel = todo;
+                int c_lane = (int)__ffsll((unsigned long long)todo) - 1;
+                if constexpr (S == 2) {
+                    float dn = 0.f;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        const float d_ = qp.v[a] - __shfl(qp.v[a], c_lane, kWave);
+                        dn = fmaf(d_, d_, dn);
+                    }
+                    peel = __ballot(((todo >> lane) & 1ull) && (double)dn <= kTilePeel * r0 * r0);
+                    peel |= 1ull << c_lane;
+                    if (peel != whole) // a later peel, or a part of the range: its own box
+                        range_box(peel, r0, box_lo, box_hi);
                 }
-                bool all = true;
-    #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
-                const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
-                R2 = (float)R2d;
-                if (!all)
-                    R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
-                R2 = fmaxf(R2, 1e-30f);
-                s0b = (float)kBins / R2;
-                for (int w = 0; w < kBinWords; ++w)
-                    hist[w * kWave + lane] = 0u;
-                total = 0;
-                __syncthreads();
-                n_streamed += stream_box<T, NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, qp, q, act,
-                              [&](float f, const Pt<T> &c, int pos, int idx) {
-                                  if (f <= R2) {
-                                      ++total;
-                                      const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
-                                      atomicAdd(&hist[(bb >> 1) * kWave + lane], 1u << ((bb & 1) * 16));
-                                  }
-                              });
-                const bool short_lane = act && total < K;
-                if (__ballot(short_lane) == 0 || all) {
-                    if (short_lane)
-                        atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
-                    break;
-                }
-                R *= 1.3;
-            }
-
-            // ----- locate the bin of the K-th neighbour ------------------------------------------
-            const bool overflow = total >= 0xffff; // 16-bit counters saturated: exhaustive path
-            int below = 0, b0 = kBins - 1, in_b0 = 0;
-            {
-                int cum = 0;
-                bool found = false;
-                for (int w = 0; w < kBinWords; ++w) {
-                    const uint32_t h = hist[w * kWave + lane];
-                    const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
-                    if (!found) {
-                        if (cum + c0 >= K) {
-                            found = true; b0 = 2 * w; below = cum; in_b0 = c0;
-                        } else if (cum + c0 + c1 >= K) {
-                            found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
+                todo &= ~peel;
+                const bool act = (peel >> lane) & 1ull;
+                ++n_sub;
+                int nin = 0, nb = 0;  // sure neighbours written, boundary candidates
+                int keep_s = 0;       // slow path: sure neighbours it keeps
+                float lo_s = 0.f;     // slow path: culling distances below it are kept sure neighbours
+                float hi_s = 0.f;     // slow path: culling distances above it are never neighbours
+                bool force_slow = false;
+                int nbox_lo[3], nbox_hi[3];
+                if constexpr (S == 2) {
+                    // ===== tile search: g(query, candidate) from the matrix cores (float points) =====
+                    const int hl = lane >> 5, ll = lane & 31;
+                    int32_t *cnt_in = (int32_t *)(lds_stage + kTileStage + kWave * 8);
+                    int32_t *cnt_bd = cnt_in + kWave;
+                    // centre: the peel's first query; query operands (-2 q^, 1, |q^|^2)
+                    float cq[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        cq[a] = __shfl(qp.v[a], c_lane, kWave);
+                    float qh[4], nq = 0.f;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        qh[a] = qp.v[a] - cq[a];
+                        nq = fmaf(qh[a], qh[a], nq);
+                    }
+                    float *qaug = (float *)lds_stage; // the candidate operand area, free between streams
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        qaug[a * kWave + lane] = -2.f * qh[a];
+                    qaug[4 * kWave + lane] = 1.f;
+                    qaug[5 * kWave + lane] = nq;
+                    __syncthreads();
+                    float bq[2][3];
+#pragma unroll
+                    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+                        for (int s = 0; s < 3; ++s)
+                            bq[qb][s] = qaug[(2 * s + hl) * kWave + 32 * qb + ll];
+                    __syncthreads();
+                    const double ed = (double)e, E = (double)kTileErr, nqd = (double)nq;
+                    // the pair (query, itself) has g in [0, gself]
+                    const double gself = 5.0 * E * nqd;
+                    // ----- pass 1: histogram of g; grow the radius until every active lane counts K ---
+                    double R = r0;
+                    float R2u = 0.f, s0b = 0.f, cut = -INFINITY;
+                    int total = 0, streamed1 = 0;
+                    for (int grow = 0;; ++grow) {
+                        if (grow > 0) {
+                            range_box(peel, R, box_lo, box_hi);
+                            ++n_grow;
                         }
-                        cum += c0 + c1;
+                        bool all = true;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
+                        const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
+                        R2u = fmaxf((float)R2d, 1e-30f);
+                        s0b = (float)kBins / R2u;
+                        // g <= cut implies key <= R2d (inside the box's radius); over the whole grid every
+                        // point passes
+                        cut = !act ? -INFINITY
+                                   : all ? f32_up((R2d * kTileU1 + kTileU0 * nqd) * (1.0 + 1e-6))
+                                         : f32_down(R2d * (1.0 - ed) - E * nqd);
+                        for (int w = 0; w < kBinWords; ++w)
+                            hist[w * kWave + lane] = 0u;
+                        __syncthreads();
+                        const float cut0 = __shfl(cut, ll, kWave), cut1 = __shfl(cut, 32 + ll, kWave);
+                        streamed1 = stream_tile<NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq,
+                            [&](int cb, int qb, const floatx16 &acc) {
+                                const float c_ = qb ? cut1 : cut0;
+                                uint32_t *h = hist + 32 * qb + ll;
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) {
+                                    const float gv = acc[r];
+                                    const int bb = (int)fminf(fmaxf(gv * s0b, 0.f), (float)(kBins - 1));
+                                    if (gv <= c_)
+                                        atomicAdd(&h[(bb >> 1) * kWave], 1u << ((bb & 1) * 16));
+                                }
+                            });
+                        n_streamed += streamed1;
+                        __syncthreads();
+                        int cntall = 0;
+                        for (int w = 0; w < kBinWords; ++w) {
+                            const uint32_t hw = hist[w * kWave + lane];
+                            cntall += (int)(hw & 0xffffu) + (int)(hw >> 16);
+                        }
+                        total = cntall - 1; // the query itself
+                        const bool short_lane = act && total < K;
+                        if (__ballot(short_lane) == 0 || all) {
+                            if (short_lane)
+                                atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
+                            break;
+                        }
+                        R *= 1.3;
                     }
-                }
-            }
-            const float wb = R2 / (float)kBins;
-            float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
-            // Later passes only need candidates with f <= hi (times the band): stream the box of the
-            // largest such radius over the range's lanes instead of the pass-1 box.
-            int nbox_lo[3], nbox_hi[3];
-            {
-                const float hmax = seg_max(act ? (overflow ? R2 : hi_f) : 0.f, kWave);
-                const double rn = sqrt((double)hmax * (1.0 + 4.0 * (double)e)) * (1.0 + 1e-5);
-                if (rn < R)
-                    range_box(ra, rb, rn, nbox_lo, nbox_hi);
-                else
-                    for (int a = 0; a < 3; ++a) {
-                        nbox_lo[a] = box_lo[a];
-                        nbox_hi[a] = box_hi[a];
-                    }
-            }
-            // ----- optional refinement inside bin b0 ---------------------------------------------
-            const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
-            if (__ballot(refine) != 0) {
-                const float base_lo = lo_f;
-                const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
-                for (int w = 0; w < kBinWords; ++w)
-                    hist[w * kWave + lane] = 0u;
-                __syncthreads();
-                n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, refine,
-                              [&](float f, const Pt<T> &c, int pos, int idx) {
-                                  if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
-                                      return;
-                                  int sb = (int)((f - base_lo) * s1);
-                                  sb = sb < 0 ? 0 : (sb > kBins - 1 ? kBins - 1 : sb);
-                                  atomicAdd(&hist[(sb >> 1) * kWave + lane], 1u << ((sb & 1) * 16));
-                              });
-                if (refine) {
-                    int cum = below, b1 = kBins - 1;
-                    bool found = false;
-                    for (int w = 0; w < kBinWords; ++w) {
-                        const uint32_t h = hist[w * kWave + lane];
-                        const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
-                        if (!found) {
-                            if (cum + c0 >= K) {
-                                found = true; b1 = 2 * w;
-                            } else if (cum + c0 + c1 >= K) {
-                                found = true; b1 = 2 * w + 1;
+                    // the query itself must sit in bin 0 of its own histogram
+                    const bool self_ok = gself * (double)s0b < 1.0 && gself <= (double)cut;
+                    force_slow = act && !self_ok;
+                    // ----- the bin of the K-th neighbour (counts at most 16 bits unless overflowed) ---
+                    const bool overflow = streamed1 >= 0xffff;
+                    int below = 0, b0 = kBins - 1, in_b0 = 0;
+                    {
+                        int cum = -1; // the query itself, in bin 0
+                        bool found = false;
+                        for (int w = 0; w < kBinWords; ++w) {
+                            const uint32_t h = hist[w * kWave + lane];
+                            const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                            if (!found) {
+                                if (cum + c0 >= K) {
+                                    found = true; b0 = 2 * w; below = cum; in_b0 = c0;
+                                } else if (cum + c0 + c1 >= K) {
+                                    found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
+                                }
+                                cum += c0 + c1;
                             }
-                            cum += c0 + c1;
                         }
                     }
-                    const float w1 = (hi_f - base_lo) / (float)kBins;
-                    const float nlo = base_lo + (float)b1 * w1;
-                    const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
-                    lo_f = nlo;
-                    hi_f = nhi;
-                }
-            }
-            if (overflow) { // everything within R is a boundary candidate
-                lo_f = 0.f;
-                hi_f = R2;
-            }
-            // ----- pass 2: classify --------------------------------------------------------------
-            const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
-            int nin = 0, nb = 0;
-            n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, act,
-                          [&](float f, const Pt<T> &c, int pos, int idx) {
-                              if (f * (1.f + e) < lo_t) {
-                                  if (nin < K)
-                                      lst[nin * ls] = idx;
-                                  ++nin;
-                              } else if (f * (1.f - e) <= hi_t) {
-                                  if (nb < kBndCap) {
-                                      bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
-                                      bndpos[nb * kWave + lane] = idx;
-                                  }
-                                  ++nb;
-                              }
-                          });
-            if (act && nin >= K)
-                atomicAdd(&P.counters[2], 1ull); // cannot happen (fewer than K below the K-th bin)
-            const int r = K - nin;
-            const bool slow = act && (nb > kBndCap || nb < r || nin >= K);
-            // ----- resolve the boundary by exact (key, index) rank --------------------------------
-            if (act && !slow) {
-                for (int bi = 0; bi < nb; ++bi) {
-                    const double kb = bndkey[bi * kWave + lane];
-                    const int pb = bndpos[bi * kWave + lane]; // original index
-                    int rank = 0;
-                    for (int bj = 0; bj < nb; ++bj) {
-                        const double kj = bndkey[bj * kWave + lane];
-                        if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
-                            ++rank;
+                    // bin edges in g, widened by the rounding of g * s0b (absolute 1e-6 R2u)
+                    const float wb = R2u / (float)kBins;
+                    float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? cut : (float)(b0 + 1) * wb;
+                    const double slack = 1e-6 * (double)R2u;
+                    double lo_e = overflow ? -1.0 : (double)lo_f - slack;
+                    double hi_e = overflow ? (double)cut : (double)hi_f + slack;
+                    {
+                        // the K nearest lie within key (hi_e + E |q^|^2) / (1 - e): stream that box only
+                        const double kb = (hi_e + E * nqd) / (1.0 - ed);
+                        const double kmax = seg_max(act ? kb : 0.0, kWave);
+                        const double rn = sqrt(kmax) * (1.0 + 1e-5);
+                        if (rn < R)
+                            range_box(peel, rn, nbox_lo, nbox_hi);
+                        else
+                            for (int a = 0; a < 3; ++a) {
+                                nbox_lo[a] = box_lo[a];
+                                nbox_hi[a] = box_hi[a];
+                            }
                     }
-                    if (rank < r)
-                        lst[(nin + rank) * ls] = pb;
-                }
-            }
-            // ----- exhaustive extraction for lanes that need it ----------------------------------
-            if (__ballot(slow) != 0) {
-                const int nin_s = slow ? (nin < K ? nin : 0) : 0;
-                const int rr = slow ? K - nin_s : 0;
-                const float lo_s = (slow && nin < K) ? lo_t : 0.f;
-                const int rmax = seg_max(rr, kWave);
-                double last_k = -1.0;
-                int last_i = -1;
-                for (int sidx = 0; sidx < rmax; ++sidx) {
-                    double best_k = INFINITY;
-                    int best_i = 0x7fffffff, best_p = -1;
-                    const bool want = slow && sidx < rr;
-                    n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, want,
+                    // ----- optional refinement inside bin b0 ------------------------------------------
+                    const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
+                    if (__ballot(refine) != 0) {
+                        const float base_lo = lo_f;
+                        const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
+                        if (refine && b0 == 0 && !(gself * (double)s1 < 1.0))
+                            force_slow = true; // the query itself must sit in sub-bin 0
+                        for (int w = 0; w < kBinWords; ++w)
+                            hist[w * kWave + lane] = 0u;
+                        __syncthreads();
+                        const float rc = refine ? cut : -INFINITY;
+                        const float rc0 = __shfl(rc, ll, kWave), rc1 = __shfl(rc, 32 + ll, kWave);
+                        const int rb0 = __shfl(b0, ll, kWave), rb1 = __shfl(b0, 32 + ll, kWave);
+                        const float bl0 = __shfl(base_lo, ll, kWave), bl1 = __shfl(base_lo, 32 + ll, kWave);
+                        const float s10 = __shfl(s1, ll, kWave), s11 = __shfl(s1, 32 + ll, kWave);
+                        n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq,
+                            [&](int cb, int qb, const floatx16 &acc) {
+                                const float c_ = qb ? rc1 : rc0, bl_ = qb ? bl1 : bl0, s1_ = qb ? s11 : s10;
+                                const int b_ = qb ? rb1 : rb0;
+                                uint32_t *h = hist + 32 * qb + ll;
+#pragma unroll
+                                for (int r = 0; r < 16; ++r) {
+                                    const float gv = acc[r];
+                                    const int bb = (int)fminf(fmaxf(gv * s0b, 0.f), (float)(kBins - 1));
+                                    if (gv <= c_ && bb == b_) {
+                                        const int sb2 = (int)fminf(fmaxf((gv - bl_) * s1_, 0.f),
+                                                                   (float)(kBins - 1));
+                                        atomicAdd(&h[(sb2 >> 1) * kWave], 1u << ((sb2 & 1) * 16));
+                                    }
+                                }
+                            });
+                        __syncthreads();
+                        if (refine) {
+                            int cum = below, b1 = kBins - 1;
+                            bool found = false;
+                            for (int w = 0; w < kBinWords; ++w) {
+                                const uint32_t h = hist[w * kWave + lane];
+                                const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                                if (!found) {
+                                    if (cum + c0 >= K) {
+                                        found = true; b1 = 2 * w;
+                                    } else if (cum + c0 + c1 >= K) {
+                                        found = true; b1 = 2 * w + 1;
+                                    }
+                                    cum += c0 + c1;
+                                }
+                            }
+                            const float w1 = (hi_f - base_lo) / (float)kBins;
+                            const float nlo = base_lo + (float)b1 * w1;
+                            const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
+                            lo_e = (double)nlo - slack;
+                            hi_e = (double)nhi + slack;
+                        }
+                    }
+                    // ----- pass 2: classify by g --------------------------------------------------------
+                    // boundary: every point with key <= kb2 (the K-th neighbour's bound) has g <= hic;
+                    // sure: g < loc implies that every point at least as near has g < lo_e, so it was
+                    // counted below the K-th neighbour's bin.
+                    const double kb2 = (hi_e + E * nqd) / (1.0 - ed);
+                    const float hic = act ? f32_up((kb2 * kTileU1 + kTileU0 * nqd) * (1.0 + 1e-6)) : -INFINITY;
+                    const double lo_k = ((lo_e - kTileU0 * nqd) / kTileU1) * (1.0 - ed) - E * nqd;
+                    const float loc = act ? f32_down(lo_k - 1e-6 * fabs(lo_k)) : -INFINITY;
+                    cnt_in[lane] = 0;
+                    cnt_bd[lane] = 0;
+                    __syncthreads();
+                    const float hc0 = __shfl(hic, ll, kWave), hc1 = __shfl(hic, 32 + ll, kWave);
+                    const float lc0 = __shfl(loc, ll, kWave), lc1 = __shfl(loc, 32 + ll, kWave);
+                    const int qi0 = __shfl(qidx, ll, kWave), qi1 = __shfl(qidx, 32 + ll, kWave);
+                    Pt<float> qq0, qq1;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        qq0.v[a] = __shfl(qp.v[a], ll, kWave);
+                        qq1.v[a] = __shfl(qp.v[a], 32 + ll, kWave);
+                    }
+                    const int32_t *st_pos = (const int32_t *)(lds_stage + 6 * kWave * 4);
+                    const int32_t *st_idx = st_pos + kWave;
+                    n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq,
+                        [&](int cb, int qb, const floatx16 &acc) {
+                            const float hc = qb ? hc1 : hc0, lc = qb ? lc1 : lc0;
+                            const int qi = qb ? qi1 : qi0;
+                            const int jb = 32 * qb + ll;
+#pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const float gv = acc[r];
+                                if (gv <= hc) {
+                                    const int ci = 32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3);
+                                    const int idx = st_idx[ci];
+                                    if (idx != qi && idx != 0x7fffffff) {
+                                        if (gv < lc) {
+                                            const int slot = atomicAdd(&cnt_in[jb], 1);
+                                            if (slot < K)
+                                                P.ell_col[(int64_t)(slot + 1) * ls + s0 + jb] = idx;
+                                        } else {
+                                            const int slot = atomicAdd(&cnt_bd[jb], 1);
+                                            if (slot < kBndCap) {
+                                                bndkey[slot * kWave + jb] =
+                                                    exact_key<float, NA>(qb ? qq1 : qq0, spts[st_pos[ci]]);
+                                                bndpos[slot * kWave + jb] = idx;
+                                            }
+                                        }
+                                    }
+                                }
+                            }
+                        });
+                    __syncthreads();
+                    nin = cnt_in[lane];
+                    nb = cnt_bd[lane];
+                    keep_s = 0;
+                    lo_s = 0.f;
+                    hi_s = f32_up(kb2 * (1.0 + 3.0 * ed));
+                } else {
+                    // ----- pass 1: histogram; grow the radius until every active lane counts K -----------
+                    double R = r0;
+                    float R2 = 0.f, s0b = 0.f;
+                    int total = 0;
+                    for (int grow = 0;; ++grow) {
+                        if (grow > 0) {
+                            range_box(peel, R, box_lo, box_hi);
+                            ++n_grow;
+                        }
+                        bool all = true;
+            #pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
+                        const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
+                        R2 = (float)R2d;
+                        if (!all)
+                            R2 = fminf(R2, (float)(R2d * (1.0 - 1e-6)));
+                        R2 = fmaxf(R2, 1e-30f);
+                        s0b = (float)kBins / R2;
+                        for (int w = 0; w < kBinWords; ++w)
+                            hist[w * kWave + lane] = 0u;
+                        total = 0;
+                        __syncthreads();
+                        n_streamed += stream_box<T, NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, qp, q, act,
+                                      [&](float f, const Pt<T> &c, int pos, int idx) {
+                                          if (f <= R2) {
+                                              ++total;
+                                              const int bb = max(0, min(kBins - 1, (int)(f * s0b)));
+                                              atomicAdd(&hist[(bb >> 1) * kWave + lane], 1u << ((bb & 1) * 16));
+                                          }
+                                      });
+                        const bool short_lane = act && total < K;
+                        if (__ballot(short_lane) == 0 || all) {
+                            if (short_lane)
+                                atomicAdd(&P.counters[2], 1ull); // cannot happen: every cloud has > K points
+                            break;
+                        }
+                        R *= 1.3;
+                    }
+
+                    // ----- locate the bin of the K-th neighbour ------------------------------------------
+                    const bool overflow = total >= 0xffff; // 16-bit counters saturated: exhaustive path
+                    int below = 0, b0 = kBins - 1, in_b0 = 0;
+                    {
+                        int cum = 0;
+                        bool found = false;
+                        for (int w = 0; w < kBinWords; ++w) {
+                            const uint32_t h = hist[w * kWave + lane];
+                            const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                            if (!found) {
+                                if (cum + c0 >= K) {
+                                    found = true; b0 = 2 * w; below = cum; in_b0 = c0;
+                                } else if (cum + c0 + c1 >= K) {
+                                    found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
+                                }
+                                cum += c0 + c1;
+                            }
+                        }
+                    }
+                    const float wb = R2 / (float)kBins;
+                    float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? R2 : (float)(b0 + 1) * wb;
+                    // Later passes only need candidates with f <= hi (times the band): stream the box of the
+                    // largest such radius over the range's lanes instead of the pass-1 box.
+                    {
+                        const float hmax = seg_max(act ? (overflow ? R2 : hi_f) : 0.f, kWave);
+                        const double rn = sqrt((double)hmax * (1.0 + 4.0 * (double)e)) * (1.0 + 1e-5);
+                        if (rn < R)
+                            range_box(peel, rn, nbox_lo, nbox_hi);
+                        else
+                            for (int a = 0; a < 3; ++a) {
+                                nbox_lo[a] = box_lo[a];
+                                nbox_hi[a] = box_hi[a];
+                            }
+                    }
+                    // ----- optional refinement inside bin b0 ---------------------------------------------
+                    const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
+                    if (__ballot(refine) != 0) {
+                        const float base_lo = lo_f;
+                        const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
+                        for (int w = 0; w < kBinWords; ++w)
+                            hist[w * kWave + lane] = 0u;
+                        __syncthreads();
+                        n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, refine,
+                                      [&](float f, const Pt<T> &c, int pos, int idx) {
+                                          if (!(f <= R2) || max(0, min(kBins - 1, (int)(f * s0b))) != b0)
+                                              return;
+                                          int sb = (int)((f - base_lo) * s1);
+                                          sb = sb < 0 ? 0 : (sb > kBins - 1 ? kBins - 1 : sb);
+                                          atomicAdd(&hist[(sb >> 1) * kWave + lane], 1u << ((sb & 1) * 16));
+                                      });
+                        if (refine) {
+                            int cum = below, b1 = kBins - 1;
+                            bool found = false;
+                            for (int w = 0; w < kBinWords; ++w) {
+                                const uint32_t h = hist[w * kWave + lane];
+                                const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
+                                if (!found) {
+                                    if (cum + c0 >= K) {
+                                        found = true; b1 = 2 * w;
+                                    } else if (cum + c0 + c1 >= K) {
+                                        found = true; b1 = 2 * w + 1;
+                                    }
+                                    cum += c0 + c1;
+                                }
+                            }
+                            const float w1 = (hi_f - base_lo) / (float)kBins;
+                            const float nlo = base_lo + (float)b1 * w1;
+                            const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
+                            lo_f = nlo;
+                            hi_f = nhi;
+                        }
+                    }
+                    if (overflow) { // everything within R is a boundary candidate
+                        lo_f = 0.f;
+                        hi_f = R2;
+                    }
+                    // ----- pass 2: classify --------------------------------------------------------------
+                    const float lo_t = lo_f * (1.f - e), hi_t = hi_f * (1.f + e);
+                    n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, act,
                                   [&](float f, const Pt<T> &c, int pos, int idx) {
-                                      if (!(f * (1.f - e) <= hi_t) || f * (1.f + e) < lo_s)
-                                          return;
-                                      const double k = exact_key<T, NA>(qp, c);
-                                      const bool after = k > last_k || (k == last_k && idx > last_i);
-                                      const bool better = k < best_k || (k == best_k && idx < best_i);
-                                      if (after && better) {
-                                          best_k = k; best_i = idx; best_p = pos;
+                                      if (f * (1.f + e) < lo_t) {
+                                          if (nin < K)
+                                              lst[nin * ls] = idx;
+                                          ++nin;
+                                      } else if (f * (1.f - e) <= hi_t) {
+                                          if (nb < kBndCap) {
+                                              bndkey[nb * kWave + lane] = exact_key<T, NA>(qp, c);
+                                              bndpos[nb * kWave + lane] = idx;
+                                          }
+                                          ++nb;
                                       }
                                   });
-                    if (want) {
-                        lst[(nin_s + sidx) * ls] = best_p < 0 ? qidx : best_i;
-                        last_k = best_k;
-                        last_i = best_i;
-                        if (best_i == 0x7fffffff)
-                            atomicAdd(&P.counters[2], 1ull);
+                    keep_s = nin < K ? nin : 0;
+                    lo_s = nin < K ? lo_t : 0.f;
+                    hi_s = hi_t;
+                }
+                if (act && nin >= K)
+                    atomicAdd(&P.counters[2], 1ull); // cannot happen (fewer than K below the K-th bin)
+                const int r = K - nin;
+                const bool slow = act && (force_slow || nb > kBndCap || nb < r || nin >= K);
+                // ----- resolve the boundary by exact (key, index) rank --------------------------------
+                if (act && !slow) {
+                    for (int bi = 0; bi < nb; ++bi) {
+                        const double kb = bndkey[bi * kWave + lane];
+                        const int pb = bndpos[bi * kWave + lane]; // original index
+                        int rank = 0;
+                        for (int bj = 0; bj < nb; ++bj) {
+                            const double kj = bndkey[bj * kWave + lane];
+                            if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
+                                ++rank;
+                        }
+                        if (rank < r)
+                            lst[(nin + rank) * ls] = pb;
                     }
                 }
-                if (slow)
-                    slow_row = true;
+                // ----- exhaustive extraction for lanes that need it ----------------------------------
+                if (__ballot(slow) != 0) {
+                    const int nin_s = slow ? keep_s : 0;
+                    const int rr = slow ? K - nin_s : 0;
+                    const float lo_sl = slow ? lo_s : 0.f;
+                    const int rmax = seg_max(rr, kWave);
+                    double last_k = -1.0;
+                    int last_i = -1;
+                    for (int sidx = 0; sidx < rmax; ++sidx) {
+                        double best_k = INFINITY;
+                        int best_i = 0x7fffffff, best_p = -1;
+                        const bool want = slow && sidx < rr;
+                        n_streamed += stream_box<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, qp, q, want,
+                                      [&](float f, const Pt<T> &c, int pos, int idx) {
+                                          if (!(f * (1.f - e) <= hi_s) || f * (1.f + e) < lo_sl)
+                                              return;
+                                          const double k = exact_key<T, NA>(qp, c);
+                                          const bool after = k > last_k || (k == last_k && idx > last_i);
+                                          const bool better = k < best_k || (k == best_k && idx < best_i);
+                                          if (after && better) {
+                                              best_k = k; best_i = idx; best_p = pos;
+                                          }
+                                      });
+                        if (want) {
+                            lst[(nin_s + sidx) * ls] = best_p < 0 ? qidx : best_i;
+                            last_k = best_k;
+                            last_i = best_i;
+                            if (best_i == 0x7fffffff)
+                                atomicAdd(&P.counters[2], 1ull);
+                        }
+                    }
+                    if (slow)
+                        slow_row = true;
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 

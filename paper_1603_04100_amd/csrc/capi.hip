@@ -269,8 +269,42 @@ void *staging(size_t bytes)
 }
 
 // Occupancy of the persistent assembly kernel (blocks per CU) per (precision, n, K), queried once.
-std::atomic<int> g_occupancy[2][3][2]; // [double][n - 2][lane search]
+std::atomic<int> g_occupancy[2][3][3]; // [double][n - 2][search mode]
 std::atomic<int> g_n_cu{0};
+
+// Persistent search kernel of a mode (0 group, 1 lane, 2 tile; tile only for float points).
+template <typename T, int NA>
+const void *search_kernel_ptr(int smode)
+{
+    if constexpr (sizeof(T) == 4)
+        if (smode == 2)
+            return (const void *)search_persistent_kernel<T, NA, 2>;
+    return smode == 1 ? (const void *)search_persistent_kernel<T, NA, 1>
+                      : (const void *)search_persistent_kernel<T, NA, 0>;
+}
+
+template <typename T, int NA>
+void launch_search(int smode, bool persistent, unsigned nblk, size_t lds, hipStream_t stream,
+                   const AsmParams &ap)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (smode == 2) {
+            if (persistent)
+                search_persistent_kernel<T, NA, 2><<<nblk, kWave, lds, stream>>>(ap);
+            else
+                search_kernel<T, NA, 2><<<nblk, kWave, lds, stream>>>(ap);
+            return;
+        }
+    }
+    if (persistent && smode == 1)
+        search_persistent_kernel<T, NA, 1><<<nblk, kWave, lds, stream>>>(ap);
+    else if (persistent)
+        search_persistent_kernel<T, NA, 0><<<nblk, kWave, lds, stream>>>(ap);
+    else if (smode == 1)
+        search_kernel<T, NA, 1><<<nblk, kWave, lds, stream>>>(ap);
+    else
+        search_kernel<T, NA, 0><<<nblk, kWave, lds, stream>>>(ap);
+}
 
 template <typename T>
 mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<int64_t> &offs,
@@ -521,19 +555,18 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.counters = L->counters;
     ap.queue = d_queue;
     const int d = p.d_manifold;
-    const int lane_search = p.search == MVGD_SEARCH_LANE ? 1 : 0;
-    const size_t lds = (size_t)search_lds_bytes((int)sizeof(Pt<T>), !lane_search);
+    // search mode: 0 group, 1 lane, 2 tile (float points only; rejected for FP64 by validate)
+    const int smode = p.search == MVGD_SEARCH_LANE ? 1 : (p.search == MVGD_SEARCH_TILE ? 2 : 0);
+    const size_t lds = (size_t)search_lds_bytes((int)sizeof(Pt<T>), smode);
     const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
     unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
     if (persistent) {
-        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb - 2][lane_search];
+        std::atomic<int> &occ = g_occupancy[sizeof(T) == 8][n_amb - 2][smode];
         int per_cu = occ.load(), n_cu = g_n_cu.load();
         if (per_cu <= 0 || n_cu <= 0) {
-#define MVGD_PK(NA_)                                                                              \
-    (lane_search ? (const void *)search_persistent_kernel<T, NA_, 1>                              \
-                 : (const void *)search_persistent_kernel<T, NA_, 0>)
-            const void *kern = n_amb == 4 ? MVGD_PK(4) : n_amb == 3 ? MVGD_PK(3) : MVGD_PK(2);
-#undef MVGD_PK
+            const void *kern = n_amb == 4   ? search_kernel_ptr<T, 4>(smode)
+                               : n_amb == 3 ? search_kernel_ptr<T, 3>(smode)
+                                            : search_kernel_ptr<T, 2>(smode);
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds) != hipSuccess ||
                 hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
                 return fail(MVGD_EDEVICE, "occupancy query failed");
@@ -548,24 +581,12 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     if (L->ev[1])
         (void)hipEventRecord(L->ev[1], stream);
     // neighbour search: lists of original indices into ELL slots 1..K
-#define MVGD_SEARCH(NA_)                                                                          \
-    do {                                                                                          \
-        if (persistent && lane_search)                                                            \
-            search_persistent_kernel<T, NA_, 1><<<nblk, kWave, lds, stream>>>(ap);                \
-        else if (persistent)                                                                      \
-            search_persistent_kernel<T, NA_, 0><<<nblk, kWave, lds, stream>>>(ap);                \
-        else if (lane_search)                                                                     \
-            search_kernel<T, NA_, 1><<<nblk, kWave, lds, stream>>>(ap);                           \
-        else                                                                                      \
-            search_kernel<T, NA_, 0><<<nblk, kWave, lds, stream>>>(ap);                           \
-    } while (0)
     if (n_amb == 4)
-        MVGD_SEARCH(4);
+        launch_search<T, 4>(smode, persistent, nblk, lds, stream, ap);
     else if (n_amb == 3)
-        MVGD_SEARCH(3);
+        launch_search<T, 3>(smode, persistent, nblk, lds, stream, ap);
     else
-        MVGD_SEARCH(2);
-#undef MVGD_SEARCH
+        launch_search<T, 2>(smode, persistent, nblk, lds, stream, ap);
     if (mvgd_status st = check_launch("neighbour search"); st != MVGD_OK)
         return st;
     if (L->ev[5])
@@ -622,8 +643,10 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
         return fail(MVGD_EINVAL, "h_override must be positive and finite");
     if (p->launch < MVGD_LAUNCH_DEFAULT || p->launch > MVGD_LAUNCH_PERSISTENT)
         return fail(MVGD_EINVAL, "unknown launch mode %d", p->launch);
-    if (p->search < MVGD_SEARCH_DEFAULT || p->search > MVGD_SEARCH_LANE)
+    if (p->search < MVGD_SEARCH_DEFAULT || p->search > MVGD_SEARCH_TILE)
         return fail(MVGD_EINVAL, "unknown search mode %d", p->search);
+    if (p->search == MVGD_SEARCH_TILE && p->precision == MVGD_FP64)
+        return fail(MVGD_EUNSUPPORTED, "the tile search is for MVGD_FP32_MIXED points");
     if (p->cell_alpha < 0.0f || p->radius_mu < 0.0f || p->cells_per_point < 0.0f ||
         !std::isfinite(p->cell_alpha) || !std::isfinite(p->radius_mu) ||
         !std::isfinite(p->cells_per_point) || (p->cells_per_point > 0.0f && p->cells_per_point < 0.25f) ||

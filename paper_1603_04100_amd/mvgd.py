@@ -46,7 +46,7 @@ class mvgd_params(ctypes.Structure):
 
 
 MVGD_LAUNCH_DEFAULT, MVGD_LAUNCH_GRID, MVGD_LAUNCH_PERSISTENT = 0, 1, 2
-MVGD_SEARCH_DEFAULT, MVGD_SEARCH_GROUP, MVGD_SEARCH_LANE = 0, 1, 2
+MVGD_SEARCH_DEFAULT, MVGD_SEARCH_GROUP, MVGD_SEARCH_LANE, MVGD_SEARCH_TILE = 0, 1, 2, 3
 
 
 class mvgd_info_t(ctypes.Structure):

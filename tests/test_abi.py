@@ -64,7 +64,7 @@ def _call(mv, params, n_total=1000, offsets=None, n_clouds=1, points=0x1000, out
 @pytest.mark.parametrize("field,value,status", [
     ("k", 4, -1), ("k", 64, -1), ("n_ambient", 2, -1), ("n_ambient", 5, -1),
     ("d_manifold", 3, -1), ("d_manifold", 0, -1), ("precision", 7, -1), ("flags", 1 << 9, -1),
-    ("launch", 3, -1), ("search", 3, -1),
+    ("launch", 3, -1), ("search", 4, -1),
 ])
 def test_invalid_parameters_rejected_on_host(mv, field, value, status):
     p = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, 0, 0.0)
@@ -72,6 +72,13 @@ def test_invalid_parameters_rejected_on_host(mv, field, value, status):
     st, h = _call(mv, p)
     assert st == status and h is None
     assert mv._lib.mvgd_last_error()
+
+
+def test_tile_search_is_for_fp32(mv):
+    p = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, 0, 0.0)
+    p.search = mv.MVGD_SEARCH_TILE
+    st, h = _call(mv, p)
+    assert st == mv.MVGD_EUNSUPPORTED and h is None
 
 
 @pytest.mark.parametrize("n_amb,d,k,flags", [

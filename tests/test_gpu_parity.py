@@ -575,6 +575,24 @@ def test_flat_torus_1m_sampled(mv, precision):
     _sampled(mv, clouds.flat_torus4(1_000_000, 4, 32), precision, n_rows=400)
 
 
+@pytest.mark.parametrize("name", ["flat_torus4_1m", "torus_200k", "ellipsoids_256"])
+def test_tile_search_full_size_equals_group(mv, name):
+    """At the benchmark sizes the tile search gives the group search's matrix bit for bit (the
+    group search is compared with the oracle above)."""
+    cl = clouds.config(name)
+    P = torch.tensor(cl.points.astype(np.float32), device=DEV)
+    offs = [int(v) for v in cl.offsets] if cl.offsets.shape[0] > 2 else None
+    res = []
+    for search in (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_TILE):
+        L = mv.mvgd_assemble(P, cl.k, cloud_offsets=offs, tuning={"search": search, "launch": 2})
+        rp, col, val = mv.mvgd_csr(L)
+        res.append((col, val, mv.mvgd_info(L)))
+        L.free()
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    print(f"\n[{name} tile == group] slow-knn group {res[0][2]['n_slow_knn']}, "
+          f"tile {res[1][2]['n_slow_knn']}")
+
+
 # ----------------------------------------------------------------------------------------------
 # error paths on the device
 # ----------------------------------------------------------------------------------------------
@@ -667,11 +685,14 @@ def _lattice_with_ties():
 
 
 @pytest.mark.parametrize("case", ["flat4-fp32", "flat4-fp64", "torus-fp32", "lattice-fp64",
-                                  "dups-fp32", "helix-fp64", "batch-fp32"])
+                                  "lattice-fp32", "dups-fp32", "helix-fp64", "helix-fp32",
+                                  "batch-fp32", "sphere2d-fp32"])
 def test_search_modes_agree(mv, case):
-    """The per-lane search (every query walks its own cell box) and the group search (64 queries
-    stream their common box) select the same neighbours and give bit-identical matrices, on
-    clouds with exact ties, duplicates, curves and batches; and the oracle agrees on the sets."""
+    """The per-lane search (every query walks its own cell box), the group search (64 queries
+    stream their common box) and, for float points, the tile search (the group search with the
+    query-candidate distances from the matrix cores) select the same neighbours and give
+    bit-identical matrices, on clouds with exact ties, duplicates, curves, planar clouds and
+    batches; and the oracle agrees on the sets."""
     name, precision = case.split("-")
     d, offs, k = 2, None, 20
     if name == "flat4":
@@ -687,13 +708,18 @@ def test_search_modes_agree(mv, case):
         pts, k = np.ascontiguousarray(pts[np.random.default_rng(3).permutation(len(pts))]), 16
     elif name == "helix":
         pts, k, d = clouds.helix(5000, 73, 8).points, 8, 1
+    elif name == "sphere2d":
+        pts, k, d = clouds.circle(6000, 75, 6).points, 6, 1
     else:
         cl = clouds.ellipsoid_batch(n_clouds=5, seed=74, k=20, n_min=300, n_max=8000)
         pts, offs = cl.points, [int(v) for v in cl.offsets]
     dt = torch.float64 if precision == "fp64" else torch.float32
     P = torch.tensor(pts, dtype=dt, device=DEV)
     out = []
-    for search in (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_LANE):
+    modes = (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_LANE)
+    if precision == "fp32":
+        modes += (mv.MVGD_SEARCH_TILE,)
+    for search in modes:
         for launch in (1, 2):
             L = mv.mvgd_assemble(P, k, cloud_offsets=offs, d_manifold=d,
                                  tuning={"search": search, "launch": launch})
