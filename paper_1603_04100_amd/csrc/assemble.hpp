@@ -252,6 +252,8 @@ __device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g
 constexpr float kTileErr = 4e-6f;
 constexpr float kTileAdd = 8e-6f;
 constexpr double kTilePeel = 100.0; // queries of one tile stream lie within sqrt(kTilePeel) r0 of c
+constexpr int kTileBins = 32;       // histogram bins per query (32-bit counters)
+static_assert((kTileBins + 1) * kWave * 4 <= kLdsSearch, "tile histogram (+ past-cut row) must fit");
 constexpr double kTileC = 4e-6 + 8e-6 + 6e-8;
 constexpr double kTileU1 = 1.0 + 4e-6 + 2.0 * kTileC; // key coefficient of the upper bound on g
 constexpr double kTileU0 = 4e-6 + 2.0 * kTileC;       // |q^|^2 coefficient of the upper bound on g
@@ -263,8 +265,8 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // in block (cb, qb) lane l holds query 32 qb + l % 32 against the candidates
 // 32 cb + 8 (r / 4) + 4 (l / 32) + r % 4 in acc[r], r = 0..15 (the accumulator layout of the
 // 32x32x2 instruction). bq[qb][s] are the query operands (augmented component 2 s + l / 32 of query
-// 32 qb + l % 32). Staged entries past the end of the stream get g = +inf (never selected: every
-// threshold is at most FLT_MAX) and original index 0x7fffffff.
+// 32 qb + l % 32). Staged entries past the end of the stream get g ~ 3e38 (never selected: every
+// threshold is at most 1e38) and original index 0x7fffffff.
 // Staged sorted positions and original indices are in st_pos / st_idx for the consumer.
 template <int NA, typename F>
 __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &g, const int bmin[3],
@@ -305,7 +307,7 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
         __syncthreads();
         for (int sb = 0; sb < total; sb += kWave) {
             const int tt = sb + lane;
-            float av[6] = {0.f, 0.f, 0.f, 0.f, INFINITY, 1.f};
+            float av[6] = {0.f, 0.f, 0.f, 0.f, 3e38f, 1.f};
             int32_t pos = -1, idx = 0x7fffffff;
             if (tt < total) {
                 int lo = 0, hi = kWave - 1;
@@ -338,15 +340,18 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
                 const float a0 = st_aug[hl * kWave + 32 * cb + ll];
                 const float a1 = st_aug[(2 + hl) * kWave + 32 * cb + ll];
                 const float a2 = st_aug[(4 + hl) * kWave + 32 * cb + ll];
-#pragma unroll
-                for (int qb = 0; qb < 2; ++qb) {
-                    floatx16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                                    0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[qb][0], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[qb][1], acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[qb][2], acc, 0, 0, 0);
-                    consume(cb, qb, acc);
-                }
+                // both query blocks' chains are issued before either is consumed
+                floatx16 acc0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                                 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                floatx16 acc1 = acc0;
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[0][0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[1][0], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[0][1], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[1][1], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[0][2], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[1][2], acc1, 0, 0, 0);
+                consume(cb, 0, acc0);
+                consume(cb, 1, acc1);
             }
             __syncthreads();
         }
@@ -355,7 +360,7 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
 }
 
 // float rounded towards -inf / +inf from a double (conservative thresholds); f32_up saturates at
-// FLT_MAX, so that a threshold never admits the +inf of a sentinel
+// 1e38, so that a threshold never admits the ~3e38 of a sentinel
 __device__ __forceinline__ float f32_down(double x)
 {
     float f = (float)x;
@@ -365,7 +370,17 @@ __device__ __forceinline__ float f32_up(double x)
 {
     float f = (float)x;
     f = ((double)f < x) ? nextafterf(f, INFINITY) : f;
-    return fminf(f, 3.40282347e+38f);
+    return fminf(f, 1e38f);
+}
+
+// Byte offset of the histogram row of a tile value: row round(x s) clamped to [0, top], times one
+// row of 64 lanes. The rounding is that of fma(x, s, 2^23), whose low mantissa bits are the
+// integer; shifting by 8 drops the exponent bits and scales the row by kWave * 4 bytes.
+static_assert(kWave * 4 == 256, "row stride is 256 bytes");
+__device__ __forceinline__ uint32_t tile_bin_offset(float x, float s, float top)
+{
+    const float y = __builtin_amdgcn_fmed3f(fmaf(x, s, 8388608.f), 8388608.f, 8388608.f + top);
+    return (uint32_t)__float_as_uint(y) << 8;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1315,7 +1330,12 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                 int nbox_lo[3], nbox_hi[3];
                 if constexpr (S == 2) {
                     // ===== tile search: g(query, candidate) from the matrix cores (float points) =====
+                    // Histograms of 32 bins x 32-bit counters per query: bin b holds the g with
+                    // round(g sb) = b (half-integer edges), sb ~ 31.5 / cut of the query's own cut;
+                    // values past the cut go to a 33rd, uncounted row (the boundary index area,
+                    // unused until pass 2). The bin is read from the bits of fma(g, sb, 2^23).
                     const int hl = lane >> 5, ll = lane & 31;
+                    constexpr int NB = kTileBins;
                     int32_t *cnt_in = (int32_t *)(lds_stage + kTileStage + kWave * 8);
                     int32_t *cnt_bd = cnt_in + kWave;
                     // centre: the peel's first query; query operands (-2 q^, 1, |q^|^2)
@@ -1346,10 +1366,10 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     const double ed = (double)e, E = (double)kTileErr, nqd = (double)nq;
                     // the pair (query, itself) has g in [0, gself]
                     const double gself = 5.0 * E * nqd;
-                    // ----- pass 1: histogram of g; grow the radius until every active lane counts K ---
+                    // ----- pass 1: histogram of g; grow the radius until every active lane counts K
                     double R = r0;
-                    float R2u = 0.f, s0b = 0.f, cut = -INFINITY;
-                    int total = 0, streamed1 = 0;
+                    float cut = 0.f, sb = 0.f;
+                    int total = 0;
                     for (int grow = 0;; ++grow) {
                         if (grow > 0) {
                             range_box(peel, R, box_lo, box_hi);
@@ -1360,36 +1380,29 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                         for (int a = 0; a < 3; ++a)
                             all = all && box_lo[a] == 0 && box_hi[a] == g.dim[a] - 1;
                         const double R2d = all ? g.diam2 * (1.0 + 1e-5) + 1e-300 : R * R * (1.0 - 1e-5);
-                        R2u = fmaxf((float)R2d, 1e-30f);
-                        s0b = (float)kBins / R2u;
-                        // g <= cut implies key <= R2d (inside the box's radius); over the whole grid every
-                        // point passes
-                        cut = !act ? -INFINITY
-                                   : all ? f32_up((R2d * kTileU1 + kTileU0 * nqd) * (1.0 + 1e-6))
-                                         : f32_down(R2d * (1.0 - ed) - E * nqd);
-                        for (int w = 0; w < kBinWords; ++w)
+                        // g <= cut implies key <= R2d (inside the box's radius); over the whole grid
+                        // every point passes
+                        cut = all ? f32_up((R2d * kTileU1 + kTileU0 * nqd) * (1.0 + 1e-6))
+                                  : f32_down(R2d * (1.0 - ed) - E * nqd);
+                        cut = fmaxf(cut, 1e-30f);
+                        // round(g sb) < NB (g sb < NB - 1/2) implies g <= cut
+                        sb = act ? f32_up(((double)NB - 0.5) / (double)cut * (1.0 + 1e-6)) : 0.f;
+                        for (int w = 0; w < NB; ++w)
                             hist[w * kWave + lane] = 0u;
                         __syncthreads();
-                        const float cut0 = __shfl(cut, ll, kWave), cut1 = __shfl(cut, 32 + ll, kWave);
-                        streamed1 = stream_tile<NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq,
+                        const float sb0 = __shfl(sb, ll, kWave), sb1 = __shfl(sb, 32 + ll, kWave);
+                        n_streamed += stream_tile<NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq,
                             [&](int cb, int qb, const floatx16 &acc) {
-                                const float c_ = qb ? cut1 : cut0;
-                                uint32_t *h = hist + 32 * qb + ll;
+                                const float s_ = qb ? sb1 : sb0;
+                                char *h = (char *)(hist + 32 * qb + ll);
 #pragma unroll
-                                for (int r = 0; r < 16; ++r) {
-                                    const float gv = acc[r];
-                                    const int bb = (int)fminf(fmaxf(gv * s0b, 0.f), (float)(kBins - 1));
-                                    if (gv <= c_)
-                                        atomicAdd(&h[(bb >> 1) * kWave], 1u << ((bb & 1) * 16));
-                                }
+                                for (int r = 0; r < 16; ++r)
+                                    atomicAdd((uint32_t *)(h + tile_bin_offset(acc[r], s_, (float)NB)), 1u);
                             });
-                        n_streamed += streamed1;
                         __syncthreads();
                         int cntall = 0;
-                        for (int w = 0; w < kBinWords; ++w) {
-                            const uint32_t hw = hist[w * kWave + lane];
-                            cntall += (int)(hw & 0xffffu) + (int)(hw >> 16);
-                        }
+                        for (int w = 0; w < NB; ++w)
+                            cntall += (int)hist[w * kWave + lane];
                         total = cntall - 1; // the query itself
                         const bool short_lane = act && total < K;
                         if (__ballot(short_lane) == 0 || all) {
@@ -1400,35 +1413,27 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                         R *= 1.3;
                     }
                     // the query itself must sit in bin 0 of its own histogram
-                    const bool self_ok = gself * (double)s0b < 1.0 && gself <= (double)cut;
-                    force_slow = act && !self_ok;
-                    // ----- the bin of the K-th neighbour (counts at most 16 bits unless overflowed) ---
-                    const bool overflow = streamed1 >= 0xffff;
-                    int below = 0, b0 = kBins - 1, in_b0 = 0;
+                    force_slow = act && !(gself * (double)sb < 0.5);
+                    // ----- the bin of the K-th neighbour -------------------------------------------
+                    int below = 0, b0 = NB - 1, in_b0 = 0;
                     {
                         int cum = -1; // the query itself, in bin 0
                         bool found = false;
-                        for (int w = 0; w < kBinWords; ++w) {
-                            const uint32_t h = hist[w * kWave + lane];
-                            const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
-                            if (!found) {
-                                if (cum + c0 >= K) {
-                                    found = true; b0 = 2 * w; below = cum; in_b0 = c0;
-                                } else if (cum + c0 + c1 >= K) {
-                                    found = true; b0 = 2 * w + 1; below = cum + c0; in_b0 = c1;
-                                }
-                                cum += c0 + c1;
+                        for (int w = 0; w < NB; ++w) {
+                            const int c0 = (int)hist[w * kWave + lane];
+                            if (!found && cum + c0 >= K) {
+                                found = true; b0 = w; below = cum; in_b0 = c0;
                             }
+                            cum += c0;
                         }
                     }
-                    // bin edges in g, widened by the rounding of g * s0b (absolute 1e-6 R2u)
-                    const float wb = R2u / (float)kBins;
-                    float lo_f = (float)b0 * wb, hi_f = (b0 == kBins - 1) ? cut : (float)(b0 + 1) * wb;
-                    const double slack = 1e-6 * (double)R2u;
-                    double lo_e = overflow ? -1.0 : (double)lo_f - slack;
-                    double hi_e = overflow ? (double)cut : (double)hi_f + slack;
+                    // bin edges in g, widened by the rounding of the edges (absolute 1e-6 cut)
+                    const double slack = 1e-6 * (double)cut;
+                    const double bw = 1.0 / (double)sb;
+                    double lo_e = act ? (b0 == 0 ? -1.0 : ((double)b0 - 0.5) * bw - slack) : -1.0;
+                    double hi_e = act ? ((double)b0 + 0.5) * bw + slack : 0.0;
                     {
-                        // the K nearest lie within key (hi_e + E |q^|^2) / (1 - e): stream that box only
+                        // the K nearest lie within key (hi_e + E |q^|^2) / (1 - e): stream that box
                         const double kb = (hi_e + E * nqd) / (1.0 - ed);
                         const double kmax = seg_max(act ? kb : 0.0, kWave);
                         const double rn = sqrt(kmax) * (1.0 + 1e-5);
@@ -1440,61 +1445,54 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                                 nbox_hi[a] = box_hi[a];
                             }
                     }
-                    // ----- optional refinement inside bin b0 ------------------------------------------
-                    const bool refine = act && !overflow && in_b0 > kBndCap - 4 && hi_f > lo_f;
+                    // ----- optional refinement inside bin b0 ----------------------------------------
+                    const bool refine = act && in_b0 > kBndCap - 4;
                     if (__ballot(refine) != 0) {
-                        const float base_lo = lo_f;
-                        const float s1 = refine ? (float)kBins / (hi_f - lo_f) : 0.f;
-                        if (refine && b0 == 0 && !(gself * (double)s1 < 1.0))
+                        // sub-bin c of bin b0: round((g - base_lo) s1) = c, clamped to [0, NB - 1]
+                        const double blo = b0 == 0 ? 0.0 : ((double)b0 - 0.5) / (double)sb;
+                        const double bhi = ((double)b0 + 0.5) / (double)sb;
+                        const float base_lo = refine ? (float)blo : 0.f;
+                        const float s1 = refine ? f32_up(((double)NB - 0.5) / (bhi - (double)base_lo)) : 0.f;
+                        if (refine && b0 == 0 && !(gself * (double)s1 < 0.5))
                             force_slow = true; // the query itself must sit in sub-bin 0
-                        for (int w = 0; w < kBinWords; ++w)
+                        for (int w = 0; w < NB; ++w)
                             hist[w * kWave + lane] = 0u;
                         __syncthreads();
-                        const float rc = refine ? cut : -INFINITY;
-                        const float rc0 = __shfl(rc, ll, kWave), rc1 = __shfl(rc, 32 + ll, kWave);
+                        const float sq = refine ? sb : 0.f;
+                        const float sq0 = __shfl(sq, ll, kWave), sq1 = __shfl(sq, 32 + ll, kWave);
                         const int rb0 = __shfl(b0, ll, kWave), rb1 = __shfl(b0, 32 + ll, kWave);
                         const float bl0 = __shfl(base_lo, ll, kWave), bl1 = __shfl(base_lo, 32 + ll, kWave);
                         const float s10 = __shfl(s1, ll, kWave), s11 = __shfl(s1, 32 + ll, kWave);
                         n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq,
                             [&](int cb, int qb, const floatx16 &acc) {
-                                const float c_ = qb ? rc1 : rc0, bl_ = qb ? bl1 : bl0, s1_ = qb ? s11 : s10;
-                                const int b_ = qb ? rb1 : rb0;
-                                uint32_t *h = hist + 32 * qb + ll;
+                                const float s_ = qb ? sq1 : sq0, bl_ = qb ? bl1 : bl0, s1_ = qb ? s11 : s10;
+                                const uint32_t own = (uint32_t)(qb ? rb1 : rb0) * kWave * 4;
+                                char *h = (char *)(hist + 32 * qb + ll);
 #pragma unroll
                                 for (int r = 0; r < 16; ++r) {
                                     const float gv = acc[r];
-                                    const int bb = (int)fminf(fmaxf(gv * s0b, 0.f), (float)(kBins - 1));
-                                    if (gv <= c_ && bb == b_) {
-                                        const int sb2 = (int)fminf(fmaxf((gv - bl_) * s1_, 0.f),
-                                                                   (float)(kBins - 1));
-                                        atomicAdd(&h[(sb2 >> 1) * kWave], 1u << ((sb2 & 1) * 16));
-                                    }
+                                    const uint32_t o1 = tile_bin_offset(gv, s_, (float)NB);
+                                    const uint32_t o2 = tile_bin_offset(gv - bl_, s1_, (float)(NB - 1));
+                                    atomicAdd((uint32_t *)(h + (o1 == own ? o2 : (uint32_t)NB * kWave * 4)), 1u);
                                 }
                             });
                         __syncthreads();
                         if (refine) {
-                            int cum = below, b1 = kBins - 1;
+                            int cum = below, b1 = NB - 1;
                             bool found = false;
-                            for (int w = 0; w < kBinWords; ++w) {
-                                const uint32_t h = hist[w * kWave + lane];
-                                const int c0 = (int)(h & 0xffffu), c1 = (int)(h >> 16);
-                                if (!found) {
-                                    if (cum + c0 >= K) {
-                                        found = true; b1 = 2 * w;
-                                    } else if (cum + c0 + c1 >= K) {
-                                        found = true; b1 = 2 * w + 1;
-                                    }
-                                    cum += c0 + c1;
+                            for (int w = 0; w < NB; ++w) {
+                                const int c0 = (int)hist[w * kWave + lane];
+                                if (!found && cum + c0 >= K) {
+                                    found = true; b1 = w;
                                 }
+                                cum += c0;
                             }
-                            const float w1 = (hi_f - base_lo) / (float)kBins;
-                            const float nlo = base_lo + (float)b1 * w1;
-                            const float nhi = (b1 == kBins - 1) ? hi_f : base_lo + (float)(b1 + 1) * w1;
-                            lo_e = (double)nlo - slack;
-                            hi_e = (double)nhi + slack;
+                            lo_e = b1 == 0 ? lo_e : (double)base_lo + ((double)b1 - 0.5) / (double)s1 - slack;
+                            hi_e = b1 == NB - 1 ? hi_e
+                                                : (double)base_lo + ((double)b1 + 0.5) / (double)s1 + slack;
                         }
                     }
-                    // ----- pass 2: classify by g --------------------------------------------------------
+                    // ----- pass 2: classify by g ------------------------------------------------------
                     // boundary: every point with key <= kb2 (the K-th neighbour's bound) has g <= hic;
                     // sure: g < loc implies that every point at least as near has g < lo_e, so it was
                     // counted below the K-th neighbour's bin.
@@ -1519,27 +1517,31 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq,
                         [&](int cb, int qb, const floatx16 &acc) {
                             const float hc = qb ? hc1 : hc0, lc = qb ? lc1 : lc0;
-                            const int qi = qb ? qi1 : qi0;
-                            const int jb = 32 * qb + ll;
+                            uint32_t mh = 0, ms = 0; // hits (g <= hic) and sure ones (g < loc), bit r
 #pragma unroll
                             for (int r = 0; r < 16; ++r) {
-                                const float gv = acc[r];
-                                if (gv <= hc) {
-                                    const int ci = 32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3);
-                                    const int idx = st_idx[ci];
-                                    if (idx != qi && idx != 0x7fffffff) {
-                                        if (gv < lc) {
-                                            const int slot = atomicAdd(&cnt_in[jb], 1);
-                                            if (slot < K)
-                                                P.ell_col[(int64_t)(slot + 1) * ls + s0 + jb] = idx;
-                                        } else {
-                                            const int slot = atomicAdd(&cnt_bd[jb], 1);
-                                            if (slot < kBndCap) {
-                                                bndkey[slot * kWave + jb] =
-                                                    exact_key<float, NA>(qb ? qq1 : qq0, spts[st_pos[ci]]);
-                                                bndpos[slot * kWave + jb] = idx;
-                                            }
-                                        }
+                                mh |= (acc[r] <= hc ? 1u : 0u) << r;
+                                ms |= (acc[r] < lc ? 1u : 0u) << r;
+                            }
+                            const int qi = qb ? qi1 : qi0;
+                            const int jb = 32 * qb + ll;
+                            while (mh != 0) {
+                                const int r = __builtin_ctz(mh);
+                                mh &= mh - 1;
+                                const int ci = 32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3);
+                                const int idx = st_idx[ci];
+                                if (idx == qi || idx == 0x7fffffff)
+                                    continue;
+                                if ((ms >> r) & 1u) {
+                                    const int slot = atomicAdd(&cnt_in[jb], 1);
+                                    if (slot < K)
+                                        P.ell_col[(int64_t)(slot + 1) * ls + s0 + jb] = idx;
+                                } else {
+                                    const int slot = atomicAdd(&cnt_bd[jb], 1);
+                                    if (slot < kBndCap) {
+                                        bndkey[slot * kWave + jb] =
+                                            exact_key<float, NA>(qb ? qq1 : qq0, spts[st_pos[ci]]);
+                                        bndpos[slot * kWave + jb] = idx;
                                     }
                                 }
                             }
