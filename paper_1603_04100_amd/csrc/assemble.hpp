@@ -271,7 +271,7 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 template <int NA, typename F>
 __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &g, const int bmin[3],
                                            const int bmax[3], char *lds_rng, char *lds_stage,
-                                           const float cq[4], const float (&bq)[2][3],
+                                           const float cq[4], const float (&bq)[2][3], int qmask,
                                            F &&consume)
 {
     const int lane = lane_id();
@@ -286,10 +286,11 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
               nz = uniform(bmax[2] - bmin[2] + 1);
     const int bx0 = uniform(bmin[0]), by0 = uniform(bmin[1]), bz0 = uniform(bmin[2]);
     const int nyz = ny * nz, ncells = nx * nyz;
-    int streamed = 0;
-    for (int cbase = 0; cbase < ncells; cbase += kWave) {
+    // (first sorted position, count) of cell cbase + lane of the box
+    auto load_cells = [&](int cbase, uint32_t &st, uint32_t &cn) {
         const int t = cbase + lane;
-        uint32_t st = 0, cn = 0;
+        st = 0;
+        cn = 0;
         if (t < ncells) {
             const int x = (int)((uint32_t)t / (uint32_t)nyz);
             const int r = t - x * nyz;
@@ -299,59 +300,91 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
             st = P.cell_start[cell];
             cn = P.cell_start[cell + 1] - st;
         }
+    };
+    // the point of stream slot tt of the current cell batch (ranges in LDS), or none
+    auto load_point = [&](int tt, int total, Pt<float> &p, int32_t &pos, int32_t &idx) {
+        pos = -1;
+        idx = 0x7fffffff;
+        if (tt < total) {
+            int lo = 0, hi = kWave - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (rng_pref[mid] <= tt)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            pos = rng_start[lo] + (tt - rng_pref[lo]);
+            p = spts[pos];
+            idx = P.perm[pos];
+        }
+    };
+    int streamed = 0;
+    // The next cell batch and the next chunk of points are loaded while the current chunk is on
+    // the matrix cores.
+    uint32_t st_n, cn_n;
+    load_cells(0, st_n, cn_n);
+    for (int cbase = 0; cbase < ncells; cbase += kWave) {
+        const uint32_t st = st_n, cn = cn_n;
+        if (cbase + kWave < ncells)
+            load_cells(cbase + kWave, st_n, cn_n);
         const int incl = wave_incl_scan((int)cn);
         const int total = uniform(__shfl(incl, kWave - 1, kWave));
         streamed += total;
         rng_start[lane] = (int32_t)st;
         rng_pref[lane] = incl - (int)cn;
         __syncthreads();
+        Pt<float> p_n = {{0.f, 0.f, 0.f, 0.f}};
+        int32_t pos_n, idx_n;
+        load_point(lane, total, p_n, pos_n, idx_n);
         for (int sb = 0; sb < total; sb += kWave) {
-            const int tt = sb + lane;
             float av[6] = {0.f, 0.f, 0.f, 0.f, 3e38f, 1.f};
-            int32_t pos = -1, idx = 0x7fffffff;
-            if (tt < total) {
-                int lo = 0, hi = kWave - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (rng_pref[mid] <= tt)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                pos = rng_start[lo] + (tt - rng_pref[lo]);
-                const Pt<float> p = spts[pos];
+            if (pos_n >= 0) {
                 float np = 0.f;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    av[a] = p.v[a] - cq[a];
+                    av[a] = p_n.v[a] - cq[a];
                     np = fmaf(av[a], av[a], np);
                 }
                 av[4] = np * (1.f + kTileAdd);
-                idx = P.perm[pos];
             }
 #pragma unroll
             for (int a = 0; a < 6; ++a)
                 st_aug[a * kWave + lane] = av[a];
-            st_pos[lane] = pos;
-            st_idx[lane] = idx;
+            st_pos[lane] = pos_n;
+            st_idx[lane] = idx_n;
             __syncthreads();
+            if (sb + kWave < total)
+                load_point(sb + kWave + lane, total, p_n, pos_n, idx_n);
             const int nblk = (min(kWave, total - sb) + 31) >> 5;
             for (int cb = 0; cb < nblk; ++cb) {
                 const float a0 = st_aug[hl * kWave + 32 * cb + ll];
                 const float a1 = st_aug[(2 + hl) * kWave + 32 * cb + ll];
                 const float a2 = st_aug[(4 + hl) * kWave + 32 * cb + ll];
-                // both query blocks' chains are issued before either is consumed
                 floatx16 acc0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                                  0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                floatx16 acc1 = acc0;
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[0][0], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[1][0], acc1, 0, 0, 0);
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[0][1], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[1][1], acc1, 0, 0, 0);
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[0][2], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[1][2], acc1, 0, 0, 0);
-                consume(cb, 0, acc0);
-                consume(cb, 1, acc1);
+                if (qmask == 3) {
+                    // both query blocks' chains are issued before either is consumed
+                    floatx16 acc1 = acc0;
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[0][0], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[1][0], acc1, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[0][1], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[1][1], acc1, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[0][2], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[1][2], acc1, 0, 0, 0);
+                    consume(cb, 0, acc0);
+                    consume(cb, 1, acc1);
+                } else if (qmask == 1) { // the second query block holds no active query
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[0][0], acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[0][1], acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[0][2], acc0, 0, 0, 0);
+                    consume(cb, 0, acc0);
+                } else { // the first query block holds no active query
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bq[1][0], acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bq[1][1], acc0, 0, 0, 0);
+                    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, bq[1][2], acc0, 0, 0, 0);
+                    consume(cb, 1, acc0);
+                }
             }
             __syncthreads();
         }
@@ -1363,6 +1396,9 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                         for (int s = 0; s < 3; ++s)
                             bq[qb][s] = qaug[(2 * s + hl) * kWave + 32 * qb + ll];
                     __syncthreads();
+                    // query blocks (lanes 0..31, 32..63) that hold an active query
+                    const uint64_t actm = __ballot(act);
+                    const int qmask = ((actm & 0xffffffffull) ? 1 : 0) | ((actm >> 32) ? 2 : 0);
                     const double ed = (double)e, E = (double)kTileErr, nqd = (double)nq;
                     // the pair (query, itself) has g in [0, gself]
                     const double gself = 5.0 * E * nqd;
@@ -1391,7 +1427,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                             hist[w * kWave + lane] = 0u;
                         __syncthreads();
                         const float sb0 = __shfl(sb, ll, kWave), sb1 = __shfl(sb, 32 + ll, kWave);
-                        n_streamed += stream_tile<NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq,
+                        n_streamed += stream_tile<NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq, qmask,
                             [&](int cb, int qb, const floatx16 &acc) {
                                 const float s_ = qb ? sb1 : sb0;
                                 char *h = (char *)(hist + 32 * qb + ll);
@@ -1463,7 +1499,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                         const int rb0 = __shfl(b0, ll, kWave), rb1 = __shfl(b0, 32 + ll, kWave);
                         const float bl0 = __shfl(base_lo, ll, kWave), bl1 = __shfl(base_lo, 32 + ll, kWave);
                         const float s10 = __shfl(s1, ll, kWave), s11 = __shfl(s1, 32 + ll, kWave);
-                        n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq,
+                        n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
                             [&](int cb, int qb, const floatx16 &acc) {
                                 const float s_ = qb ? sq1 : sq0, bl_ = qb ? bl1 : bl0, s1_ = qb ? s11 : s10;
                                 const uint32_t own = (uint32_t)(qb ? rb1 : rb0) * kWave * 4;
@@ -1514,7 +1550,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     }
                     const int32_t *st_pos = (const int32_t *)(lds_stage + 6 * kWave * 4);
                     const int32_t *st_idx = st_pos + kWave;
-                    n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq,
+                    n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
                         [&](int cb, int qb, const floatx16 &acc) {
                             const float hc = qb ? hc1 : hc0, lc = qb ? lc1 : lc0;
                             uint32_t mh = 0, ms = 0; // hits (g <= hic) and sure ones (g < loc), bit r
@@ -1797,17 +1833,18 @@ __global__ __launch_bounds__(64) void fit_kernel(AsmParams P)
     fit_row<T, NA, D>(P, spts, list, lane, q, spts[q], slow_row);
 }
 
-// Occupancy target of the search kernels (waves per SIMD; 0 leaves it to the compiler). Left
-// alone, the group search takes ~213 VGPRs (2 waves per SIMD); at 3 it fits 168 VGPRs with a
-// small spill and runs ~13% faster at 1M points in R^4 (measured).
+// Occupancy target of the search kernels (waves per SIMD). Left alone, the group search takes
+// ~213 VGPRs (2 waves per SIMD); at 3 it fits 168 VGPRs with a small spill and runs ~13% faster at
+// 1M points in R^4 (measured). The tile search is held to 2.5 waves per SIMD by its LDS anyway and
+// runs ~4% faster with the 256 VGPRs of 2 (measured).
 #ifndef MVGD_SEARCH_WAVES_PER_EU
 #define MVGD_SEARCH_WAVES_PER_EU 3
 #endif
-#if MVGD_SEARCH_WAVES_PER_EU > 0
-#define MVGD_SEARCH_ATTR __attribute__((amdgpu_waves_per_eu(MVGD_SEARCH_WAVES_PER_EU)))
-#else
-#define MVGD_SEARCH_ATTR
+#ifndef MVGD_TILE_WAVES_PER_EU
+#define MVGD_TILE_WAVES_PER_EU 2
 #endif
+#define MVGD_SEARCH_ATTR                                                                          \
+    __attribute__((amdgpu_waves_per_eu(S == 2 ? MVGD_TILE_WAVES_PER_EU : MVGD_SEARCH_WAVES_PER_EU)))
 
 // Grid-mapped launch: one workgroup per group, XCD-aware remap (workgroups are dispatched to the
 // eight XCDs round-robin, so workgroup b runs on XCD b % 8; consecutive groups, which are

@@ -555,8 +555,12 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.counters = L->counters;
     ap.queue = d_queue;
     const int d = p.d_manifold;
-    // search mode: 0 group, 1 lane, 2 tile (float points only; rejected for FP64 by validate)
-    const int smode = p.search == MVGD_SEARCH_LANE ? 1 : (p.search == MVGD_SEARCH_TILE ? 2 : 0);
+    // search mode: 0 group, 1 lane, 2 tile (float points only; rejected for FP64 by validate).
+    // The default is the tile search for float points and the group search for doubles.
+    const int smode = p.search == MVGD_SEARCH_LANE   ? 1
+                      : p.search == MVGD_SEARCH_TILE ? 2
+                      : p.search == MVGD_SEARCH_GROUP ? 0
+                                                      : (sizeof(T) == 4 ? 2 : 0);
     const size_t lds = (size_t)search_lds_bytes((int)sizeof(Pt<T>), smode);
     const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
     unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
