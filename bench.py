@@ -130,6 +130,10 @@ def bench_serving(args):
     warm[-1] = serve.Request(-1, warm[-1].arrival, big.points, big.rhs, big.k)
     srv = serve.Server(precision="fp32", n_streams=4, max_batch=16)
     srv.reserve(4 * n_max)
+    # every worker serves the largest request at once (the library's pool grown for four
+    # concurrent assemblies of it), then a small mixed batch
+    srv.run([serve.Request(-2 - i, 0.0, big.points, big.rhs, big.k) for i in range(4)],
+            batching=False)
     srv.run(warm)
     base_srv = serve.Server(precision="fp64", n_streams=1, max_batch=1)
     base_srv.reserve(n_max)
@@ -409,7 +413,8 @@ def main():
     from paper_1603_04100_amd import autotune
     tun = autotune.lookup(cl.n_ambient, k, "fp32", n // (cl.offsets.shape[0] - 1))
     search = "search_persistent_kernel" if tun.get("launch", 1) == 2 else "search_kernel"
-    kernel_name = (f"{search}<float,{cl.n_ambient},{1 if tun.get('search', 1) == 2 else 0}> + "
+    smode = {1: 0, 2: 1}.get(tun.get("search", 0), 2)  # default and 3: the tile search
+    kernel_name = (f"{search}<float,{cl.n_ambient},{smode}> + "
                    f"fit_kernel<float,{cl.n_ambient},2>")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),

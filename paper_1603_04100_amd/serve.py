@@ -23,6 +23,7 @@ stream serves the batches:
 from __future__ import annotations
 
 import collections
+import gc
 import queue
 import threading
 import time
@@ -196,10 +197,14 @@ class Server:
                                self.vsize)
 
     def run(self, requests: list[Request], batching: bool = True) -> Stats:
-        """Serve requests (sorted by arrival) in real time; returns latency statistics."""
+        """Serve requests (sorted by arrival) in real time; returns latency statistics. The
+        interpreter's cyclic garbage collector is paused meanwhile (a full collection stops every
+        thread, the dispatcher included)."""
         workers = [_Worker(self, i) for i in range(len(self.streams))]
         for w in workers:
             w.start()
+        gc_was_on = gc.isenabled()
+        gc.disable()
         try:
             return self._run(requests, batching, workers)
         finally:
@@ -207,6 +212,8 @@ class Server:
                 w.inbox.put(None)
             for w in workers:
                 w.join()
+            if gc_was_on:
+                gc.enable()
 
     def _run(self, requests, batching, workers) -> Stats:
         st = Stats()
