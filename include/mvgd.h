@@ -249,6 +249,9 @@ mvgd_status mvgd_row_stats(mvgd_matrix *L, double *ratio, mvgd_row_stats_t *out,
  * All iteration vectors and scalars are double and live on the device in the matrix's cell
  * order; the host reads the residual once every check_every iterations. Inner products are
  * reduced in a fixed order, so results are reproducible run to run.
+ * BiCGSTAB's recursively updated residual can drift from b - A x over long runs: when it passes
+ * the test, the true residual of the iterate is formed, and if that one does not pass, the
+ * iteration restarts from the iterate (at most four restarts, within max_iter in all).
  * Returns MVGD_OK also when the iteration does not converge (see info->converged).
  */
 enum { MVGD_SOLVE_BICGSTAB = 0, MVGD_SOLVE_JACOBI = 1 };
@@ -267,7 +270,8 @@ typedef struct {
 
 typedef struct {
     int32_t iterations;   /* iterations (Jacobi: sweeps) performed */
-    int32_t converged;    /* 1: residual test passed, 0: max_iter reached, -1: breakdown */
+    int32_t converged;    /* 1: residual test passed (BiCGSTAB: by the true residual of the
+                             returned x), 0: max_iter reached or restarts used up, -1: breakdown */
     double rel_residual;  /* ||b - A x||_2 / ||b||_2 of the returned x, recomputed */
 } mvgd_solve_info;
 

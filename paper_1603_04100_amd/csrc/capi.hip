@@ -1088,28 +1088,51 @@ mvgd_status solve_impl(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_
         return hipMemcpyAsync(&hs, sc, sizeof hs, hipMemcpyDeviceToHost, s) == hipSuccess &&
                hipStreamSynchronize(s) == hipSuccess;
     };
+    int prior_iters = 0; // BiCGSTAB: iterations of the cycles before a restart
     if (p.method == MVGD_SOLVE_BICGSTAB) {
-        bicg_first_rho_kernel<<<1, 1, 0, s>>>(sc);
-        for (int it = 0; it < p.max_iter;) {
-            const int batch = std::min(check, p.max_iter - it);
-            for (int j = 0; j < batch; ++j, ++it) {
-                bicg_p_kernel<<<nb, kSolveThreads, 0, s>>>(n, vr, vv, vp, sc, it == 0);
-                bicg_v_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
-                                                              vp, vrh, vv, part, sc);
-                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepAlpha, part, nb, 1, sc, p.rtol);
-                bicg_s_kernel<<<nb, kSolveThreads, 0, s>>>(n, vr, vv, vs, sc);
-                bicg_t_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
-                                                              vs, vt, part, sc);
-                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepOmega, part, nb, 2, sc, p.rtol);
-                bicg_xr_kernel<<<nb, kSolveThreads, 0, s>>>(n, vp, vs, vt, vrh, vx, vr, part, sc);
-                solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepRho, part, nb, 2, sc, p.rtol);
+        // The recursively updated residual can drift from b - A x over thousands of iterations.
+        // When it passes the test, the true residual is formed; if that one fails, BiCGSTAB restarts
+        // from the current iterate (at most kMaxRestarts times).
+        constexpr int kMaxRestarts = 4;
+        for (int cycle = 0;; ++cycle) {
+            const int budget = p.max_iter - prior_iters;
+            bicg_first_rho_kernel<<<1, 1, 0, s>>>(sc);
+            for (int it = 0; it < budget;) {
+                const int batch = std::min(check, budget - it);
+                for (int j = 0; j < batch; ++j, ++it) {
+                    bicg_p_kernel<<<nb, kSolveThreads, 0, s>>>(n, vr, vv, vp, sc, it == 0);
+                    bicg_v_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
+                                                                  vp, vrh, vv, part, sc);
+                    solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepAlpha, part, nb, 1, sc, p.rtol);
+                    bicg_s_kernel<<<nb, kSolveThreads, 0, s>>>(n, vr, vv, vs, sc);
+                    bicg_t_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma,
+                                                                  vs, vt, part, sc);
+                    solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepOmega, part, nb, 2, sc, p.rtol);
+                    bicg_xr_kernel<<<nb, kSolveThreads, 0, s>>>(n, vp, vs, vt, vrh, vx, vr, part, sc);
+                    solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepRho, part, nb, 2, sc, p.rtol);
+                }
+                if (mvgd_status st = check_launch("solver"); st != MVGD_OK)
+                    return st;
+                if (!read_scalars())
+                    return fail(MVGD_EDEVICE, "reading the solver state failed");
+                if (hs.done)
+                    break;
             }
+            if (hs.done != 1 || cycle == kMaxRestarts)
+                break;
+            residual_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma, vb,
+                                                            vx, part);
+            sum_partials_kernel<<<1, kSolveThreads, 0, s>>>(part, nb, &sc->dot[0]);
             if (mvgd_status st = check_launch("solver"); st != MVGD_OK)
                 return st;
             if (!read_scalars())
                 return fail(MVGD_EDEVICE, "reading the solver state failed");
-            if (hs.done)
+            if (hs.dot[0] <= hs.tol2 || prior_iters + hs.iters >= p.max_iter)
                 break;
+            prior_iters += hs.iters;
+            bicg_init_kernel<T><<<nb, kSolveThreads, 0, s>>>(col, val, n, ld, slots, pinned, sigma, vx,
+                                                             vb, vr, vrh, vp, vv, part);
+            solve_scalar_kernel<<<1, kSolveThreads, 0, s>>>(kStepInit, part, nb, 2, sc, p.rtol);
         }
     } else {
         // damped Jacobi, ping-pong between vx and vp
@@ -1143,9 +1166,12 @@ mvgd_status solve_impl(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_
         return st;
     if (!read_scalars())
         return fail(MVGD_EDEVICE, "reading the solver state failed");
-    info->iterations = hs.iters;
+    info->iterations = prior_iters + hs.iters;
     info->converged = hs.done == 1 ? 1 : hs.done == 2 ? -1 : 0;
     info->rel_residual = hs.bb > 0.0 ? sqrt(hs.dot[0] / hs.bb) : sqrt(hs.dot[0]);
+    // BiCGSTAB reports convergence only when the returned iterate's true residual passes
+    if (p.method == MVGD_SOLVE_BICGSTAB && info->converged == 1 && !(hs.dot[0] <= hs.tol2))
+        info->converged = 0;
     return MVGD_OK;
 }
 
