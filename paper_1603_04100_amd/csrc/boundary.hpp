@@ -10,8 +10,9 @@
 // is folded into its source's column.
 //
 // nm_flag_kernel     interior points with a boundary point among their K nearest neighbours
-// nm_frame_kernel    e3 at every boundary point (FP64)
-// nm_ghost_kernel    closest boundary point and mirror image of every flagged interior point
+// nm_frame_kernel    e3 at every boundary point (FP64), one wave per boundary point
+// nm_ghost_kernel    closest boundary point (among the K nearest) and mirror image of every
+//                    flagged interior point
 // nm_fold_kernel     ghost columns -> source columns; ghost rows become zero rows
 #pragma once
 
@@ -83,7 +84,9 @@ __device__ __forceinline__ void nm_eig3(double A[3][3], double W[3][3])
     jacobi_eig<3>(A, W);
 }
 
-// e3 at boundary point j (bl[j] = its index in the cloud)
+// e3 at boundary point j (bl[j] = its index in the cloud), one wave per boundary point: the kb
+// nearest boundary points are extracted in (squared distance, list index) order, one per round,
+// each round a lane-parallel scan of the boundary list and a wave argmin; lane 0 then fits.
 template <typename T>
 __global__ __launch_bounds__(64) void nm_frame_kernel(const T *__restrict__ pts,
                                                       const int32_t *__restrict__ bl, int64_t nb,
@@ -93,34 +96,47 @@ __global__ __launch_bounds__(64) void nm_frame_kernel(const T *__restrict__ pts,
                                                       int64_t ld0, int K,
                                                       double *__restrict__ e3out)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int32_t sel[16];
+    const int64_t j = blockIdx.x;
+    const int lane = (int)threadIdx.x;
     if (j >= nb)
         return;
     double pj[3];
     nm_load<T>(pts, bl[j], pj);
-    // the kb nearest boundary points (p^B_j included), by (squared distance, list index)
-    double bd[16];
-    int bi[16];
-    int cnt = 0;
-    for (int64_t t = 0; t < nb; ++t) {
-        double pt[3];
-        nm_load<T>(pts, bl[t], pt);
-        const double d = nm_d2(pj, pt);
-        if (cnt == kb && !(d < bd[kb - 1]))
-            continue;
-        int pos = cnt < kb ? cnt : kb - 1;
-        while (pos > 0 && bd[pos - 1] > d) { // strict: equal keys keep the earlier (smaller) t
-            if (pos < kb) {
-                bd[pos] = bd[pos - 1];
-                bi[pos] = bi[pos - 1];
+    double last_k = -1.0;
+    int64_t last_t = -1;
+    for (int r = 0; r < kb; ++r) {
+        double best_k = INFINITY;
+        int64_t best_t = INT64_MAX;
+        for (int64_t t = lane; t < nb; t += 64) {
+            double pt[3];
+            nm_load<T>(pts, bl[t], pt);
+            const double d = nm_d2(pj, pt);
+            const bool after = d > last_k || (d == last_k && t > last_t);
+            const bool better = d < best_k || (d == best_k && t < best_t);
+            if (after && better) {
+                best_k = d;
+                best_t = t;
             }
-            --pos;
         }
-        bd[pos] = d;
-        bi[pos] = (int)t;
-        if (cnt < kb)
-            ++cnt;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ok = __shfl_xor(best_k, o, 64);
+            const int64_t ot = __shfl_xor(best_t, o, 64);
+            if (ok < best_k || (ok == best_k && ot < best_t)) {
+                best_k = ok;
+                best_t = ot;
+            }
+        }
+        last_k = best_k;
+        last_t = best_t;
+        if (lane == 0) // (every round finds one: nb >= kb; the guard keeps an index in range)
+            sel[r] = best_t < nb ? (int32_t)best_t : (int32_t)j;
     }
+    __syncthreads();
+    if (lane != 0)
+        return;
+    const int cnt = kb;
+    const int32_t *bi = sel;
     // PCA of those points: tangent = largest eigenvector, n1, n2 = the others
     double c[3] = {0, 0, 0};
     for (int r = 0; r < cnt; ++r) {
@@ -228,11 +244,18 @@ __global__ __launch_bounds__(64) void nm_frame_kernel(const T *__restrict__ pts,
 }
 
 // ghost of flagged interior point f: fl[f] = its index in the cloud, irank[i] = its place in the
-// interior list; aug gets the ghost at row n_interior + f
+// interior list, brank[i] = a boundary point's place in the boundary list; aug gets the ghost at
+// row n_interior + f. The closest boundary point (ties to the smaller index) is among the point's K
+// nearest neighbours: some boundary point is, and every point before it in (key, index) order is too.
 template <typename T>
 __global__ __launch_bounds__(256) void nm_ghost_kernel(const T *__restrict__ pts,
                                                        const int32_t *__restrict__ fl, int64_t nf,
-                                                       const int32_t *__restrict__ bl, int64_t nb,
+                                                       const uint8_t *__restrict__ boundary,
+                                                       const uint32_t *__restrict__ brank,
+                                                       const int32_t *__restrict__ col0,
+                                                       const int32_t *__restrict__ perm0,
+                                                       const int32_t *__restrict__ ipos0,
+                                                       int64_t ld0, int K,
                                                        const double *__restrict__ e3,
                                                        const uint32_t *__restrict__ irank,
                                                        int64_t n_interior, T *__restrict__ aug,
@@ -242,21 +265,28 @@ __global__ __launch_bounds__(256) void nm_ghost_kernel(const T *__restrict__ pts
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf)
         return;
+    const int32_t i = fl[f];
     double p[3];
-    nm_load<T>(pts, fl[f], p);
+    nm_load<T>(pts, i, p);
+    const int64_t s = ipos0[i];
     double best = INFINITY;
-    int64_t bj = 0;
-    for (int64_t t = 0; t < nb; ++t) {
+    int32_t bc = -1;
+    for (int k = 1; k <= K; ++k) {
+        const int32_t c = perm0[col0[(int64_t)k * ld0 + s]];
+        if (!boundary[c])
+            continue;
         double q[3];
-        nm_load<T>(pts, bl[t], q);
+        nm_load<T>(pts, c, q);
         const double d = nm_d2(p, q);
-        if (d < best) { // strict: ties keep the smaller list index (= smaller cloud index)
+        if (d < best || (d == best && c < bc)) {
             best = d;
-            bj = t;
+            bc = c;
         }
     }
+    // a flagged point has a boundary neighbour; the guard keeps an index in range regardless
+    const int64_t bj = bc >= 0 ? (int64_t)brank[bc] : 0;
     double q[3];
-    nm_load<T>(pts, bl[bj], q);
+    nm_load<T>(pts, bc >= 0 ? bc : i, q);
     const double *e = e3 + bj * 3;
     const double h = (p[0] - q[0]) * e[0] + (p[1] - q[1]) * e[1] + (p[2] - q[2]) * e[2];
     for (int a = 0; a < 3; ++a) {
@@ -265,7 +295,7 @@ __global__ __launch_bounds__(256) void nm_ghost_kernel(const T *__restrict__ pts
         if (ghost_xyz)
             ghost_xyz[f * 3 + a] = g;
     }
-    ghost_src[f] = (int32_t)irank[fl[f]];
+    ghost_src[f] = (int32_t)irank[i];
 }
 
 // interior points of the cloud into rows [0, n_interior) of the augmented cloud

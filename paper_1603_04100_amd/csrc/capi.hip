@@ -784,13 +784,14 @@ mvgd_status neumann_impl(const T *points, int64_t n, const uint8_t *boundary, in
                     (long long)nbd, kb);
     if (ni < K + 1)
         return fail(MVGD_EINVAL, "%lld interior points; needs more than k = %d", (long long)ni, K);
-    if (nbd > 0)
-        nm_frame_kernel<T><<<(unsigned)((nbd + 63) / 64), 64, 0, s>>>(
-            points, bl, nbd, kb, H0->ell_col, H0->perm, ipos0, H0->ld, K, e3);
+    if (nbd > 0) // one wave per boundary point
+        nm_frame_kernel<T><<<(unsigned)nbd, 64, 0, s>>>(points, bl, nbd, kb, H0->ell_col, H0->perm,
+                                                        ipos0, H0->ld, K, e3);
     nm_gather_kernel<T><<<(unsigned)((ni + 255) / 256), 256, 0, s>>>(points, il, ni, aug);
     if (nf > 0)
         nm_ghost_kernel<T><<<(unsigned)((nf + 255) / 256), 256, 0, s>>>(
-            points, fl, nf, bl, nbd, e3, ri, ni, aug, ghost_src, ghost_xyz);
+            points, fl, nf, boundary, rb, H0->ell_col, H0->perm, ipos0, H0->ld, K, e3, ri, ni, aug,
+            ghost_src, ghost_xyz);
     if (mvgd_status st = check_launch("ghost points"); st != MVGD_OK)
         return st;
     const std::vector<int64_t> whole_aug = {0, ni + nf};
