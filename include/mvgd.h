@@ -320,6 +320,57 @@ mvgd_status mvgd_assemble_neumann(const void *points, int64_t n_total, const uin
                                   mvgd_matrix **out, double *ghost_xyz, int32_t *ghost_src,
                                   mvgd_neumann_info *info);
 
+/*
+ * mvgd_eigs -- the nev eigenvalues of -L with the smallest real parts (Sec. 4: -Delta nu = lambda
+ * nu; on the unit sphere lambda = l (l + 1) with multiplicity 2 l + 1).
+ *
+ * Method: Chebyshev-filtered subspace iteration on a block of m vectors (double, the matrix's cell
+ * order). Each iteration applies p(A), A = -L, a Chebyshev polynomial of the given degree that is
+ * bounded on [a, b] and grows below a (b: the largest absolute row sum of L, a Gershgorin bound;
+ * a: the largest Ritz value of the block), with one multi-column ELL product per degree; then
+ * orthonormalises the block (Cholesky QR, twice) and takes the eigenvalues of V^T A V (m x m,
+ * Hessenberg reduction and the double-shift QR iteration on the host) as Ritz values. L is not
+ * symmetric, so Ritz values may come in complex conjugate pairs; both parts are returned.
+ * Rows flagged in `fixed` are removed from the operator (the iteration runs on the submatrix of
+ * the other rows and columns): Dirichlet points, or the ghost rows of mvgd_assemble_neumann.
+ *
+ * lambda_re, lambda_im  host [nev], sorted by real part (then imaginary part).
+ * info                  host; the call waits for `stream` a few times per iteration.
+ * MVGD_EINVAL for parameters out of range or a matrix with at most m rows; MVGD_EDEVICE if the
+ * block loses rank or the small QR iteration fails. Returns MVGD_OK also when the iteration
+ * stops at max_iter (info->converged = 0).
+ */
+typedef struct {
+    int32_t nev;          /* eigenvalues wanted, 1..64 */
+    int32_t block;        /* subspace size m, nev..64; 0 selects min(64, max(nev + 8, 2 nev)) */
+    int32_t degree;       /* filter degree per iteration, 0..1000; 0: per iteration
+                             2 sqrt((b - a) / (a - a0)) in [8, 500] (a0: the smallest Ritz value
+                             or 0), a growth of about e^4 from a to the bottom of the spectrum */
+    int32_t max_iter;     /* filter iterations; 0 selects 500 */
+    double tol;           /* converged when the nev Ritz values move by at most tol max(1, |lambda|)
+                             in two consecutive iterations; 0 selects 1e-10 */
+    const uint8_t *fixed; /* device [n_rows] in the caller's order, nonzero = removed; NULL: none */
+    uint64_t seed;        /* start block (counter-based random numbers) */
+} mvgd_eigs_params;
+
+typedef struct {
+    int32_t iterations;
+    int32_t converged;     /* 1: the test passed, 0: max_iter reached */
+    int32_t block;         /* m used */
+    int32_t degree;        /* degree of the last iteration */
+    double spectrum_bound; /* b / 1.01 */
+    double max_change;     /* the last iteration's largest relative Ritz value change */
+} mvgd_eigs_info;
+
+mvgd_status mvgd_eigs(mvgd_matrix *L, const mvgd_eigs_params *p, double *lambda_re,
+                      double *lambda_im, mvgd_eigs_info *info, void *stream);
+
+/* mvgd_dense_eigvals -- eigenvalues of a real m x m matrix (host, row-major), the small dense step
+ * of mvgd_eigs (Householder reduction to Hessenberg form, then the implicitly double-shifted QR
+ * iteration). re, im: host [m], unordered. Host only, no device involved. MVGD_EINVAL on bad
+ * arguments or when the iteration does not converge. */
+mvgd_status mvgd_dense_eigvals(int32_t m, const double *a, double *re, double *im);
+
 /* mvgd_pool_trim -- device memory of the current device that the library keeps cached. Handles
  * and assembly scratch come from a stream-ordered pool owned by the library, one per device; freed
  * memory stays in the pool for later calls (no fresh mapping per assembly). This call returns the

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmvgd.so")
 SOURCES = ["capi.hip"]
-HEADERS = ["common.hpp", "bin.hpp", "assemble.hpp", "apply.hpp", "stats.hpp", "solve.hpp", "boundary.hpp"]
+HEADERS = ["common.hpp", "bin.hpp", "assemble.hpp", "apply.hpp", "stats.hpp", "solve.hpp", "boundary.hpp", "eigs.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <string>
@@ -20,6 +21,7 @@
 #include "bin.hpp"
 #include "boundary.hpp"
 #include "common.hpp"
+#include "eigs.hpp"
 #include "solve.hpp"
 #include "stats.hpp"
 
@@ -1176,6 +1178,372 @@ mvgd_status solve_impl(mvgd_matrix *L, const void *b, void *x, const mvgd_solve_
     return MVGD_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// small dense helpers on the host (Rayleigh-Ritz of the eigenvalue iteration)
+// ---------------------------------------------------------------------------------------------
+// Eigenvalues of a real m x m matrix (row-major): Householder reduction to upper Hessenberg form,
+// then the implicitly double-shifted QR iteration (Francis) with deflation at negligible
+// subdiagonal entries; 1 x 1 blocks give real eigenvalues, 2 x 2 blocks a real pair or a complex
+// conjugate pair. Only the active block is transformed (no Schur vectors are kept).
+// Returns false if some eigenvalue did not converge within 60 iterations.
+bool dense_eigvals(int m, const double *A, double *re, double *im)
+{
+    std::vector<double> h((size_t)m * m);
+    for (int i = 0; i < m * m; ++i)
+        h[i] = A[i];
+    auto H = [&](int i, int j) -> double & { return h[(size_t)i * m + j]; };
+    // Hessenberg reduction
+    for (int k = 0; k + 2 < m; ++k) {
+        double alpha = 0.0;
+        for (int i = k + 1; i < m; ++i)
+            alpha += H(i, k) * H(i, k);
+        alpha = std::sqrt(alpha);
+        if (alpha == 0.0)
+            continue;
+        if (H(k + 1, k) > 0.0)
+            alpha = -alpha;
+        std::vector<double> v(m, 0.0);
+        v[k + 1] = H(k + 1, k) - alpha;
+        for (int i = k + 2; i < m; ++i)
+            v[i] = H(i, k);
+        double vv = 0.0;
+        for (int i = k + 1; i < m; ++i)
+            vv += v[i] * v[i];
+        if (vv == 0.0)
+            continue;
+        // H <- (I - 2 v v^T / vv) H (I - 2 v v^T / vv)
+        for (int j = 0; j < m; ++j) {
+            double d = 0.0;
+            for (int i = k + 1; i < m; ++i)
+                d += v[i] * H(i, j);
+            d *= 2.0 / vv;
+            for (int i = k + 1; i < m; ++i)
+                H(i, j) -= d * v[i];
+        }
+        for (int i = 0; i < m; ++i) {
+            double d = 0.0;
+            for (int j = k + 1; j < m; ++j)
+                d += H(i, j) * v[j];
+            d *= 2.0 / vv;
+            for (int j = k + 1; j < m; ++j)
+                H(i, j) -= d * v[j];
+        }
+        for (int i = k + 2; i < m; ++i)
+            H(i, k) = 0.0;
+    }
+    const double eps = std::numeric_limits<double>::epsilon();
+    int hi = m - 1, iter = 0;
+    while (hi >= 0) {
+        // deflation point: the lowest l with negligible H(l, l - 1)
+        int l = hi;
+        while (l > 0) {
+            const double s = std::fabs(H(l - 1, l - 1)) + std::fabs(H(l, l));
+            if (std::fabs(H(l, l - 1)) <= eps * (s == 0.0 ? 1.0 : s))
+                break;
+            --l;
+        }
+        if (l == hi) { // 1 x 1 block
+            re[hi] = H(hi, hi);
+            im[hi] = 0.0;
+            --hi;
+            iter = 0;
+            continue;
+        }
+        if (l == hi - 1) { // 2 x 2 block: eigenvalues of [[a, b], [c, d]]
+            const double a = H(hi - 1, hi - 1), b = H(hi - 1, hi), c = H(hi, hi - 1), d = H(hi, hi);
+            const double tr = 0.5 * (a + d), det = a * d - b * c, disc = tr * tr - det;
+            if (disc >= 0.0) {
+                const double r = std::sqrt(disc);
+                const double e1 = tr + (tr >= 0.0 ? r : -r);
+                const double e2 = e1 != 0.0 ? det / e1 : tr - (tr >= 0.0 ? r : -r);
+                re[hi - 1] = e1;
+                re[hi] = e2;
+                im[hi - 1] = im[hi] = 0.0;
+            } else {
+                const double r = std::sqrt(-disc);
+                re[hi - 1] = re[hi] = tr;
+                im[hi - 1] = r;
+                im[hi] = -r;
+            }
+            hi -= 2;
+            iter = 0;
+            continue;
+        }
+        if (++iter > 60)
+            return false;
+        // double shift from the trailing 2 x 2 block (an exceptional shift every 10th iteration)
+        double s = H(hi - 1, hi - 1) + H(hi, hi);
+        double t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
+        if (iter % 10 == 0) {
+            const double w = std::fabs(H(hi, hi - 1)) + std::fabs(H(hi - 1, hi - 2));
+            s = 1.5 * w;
+            t = w * w;
+        }
+        double x = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
+        double y = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
+        double z = H(l + 1, l) * H(l + 2, l + 1);
+        for (int k = l; k <= hi - 2; ++k) {
+            // reflector P = I - 2 u u^T / (u^T u) with P (x, y, z)^T = (beta, 0, 0)^T
+            double nrm = std::sqrt(x * x + y * y + z * z);
+            if (nrm != 0.0) {
+                const double beta = x > 0.0 ? -nrm : nrm;
+                const double u0 = x - beta, u1 = y, u2 = z;
+                const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+                const int c0 = k > l ? k - 1 : l;
+                for (int j = c0; j <= hi; ++j) {
+                    const double d = 2.0 * (u0 * H(k, j) + u1 * H(k + 1, j) + u2 * H(k + 2, j)) / uu;
+                    H(k, j) -= d * u0;
+                    H(k + 1, j) -= d * u1;
+                    H(k + 2, j) -= d * u2;
+                }
+                const int r1 = std::min(k + 3, hi);
+                for (int i = l; i <= r1; ++i) {
+                    const double d = 2.0 * (H(i, k) * u0 + H(i, k + 1) * u1 + H(i, k + 2) * u2) / uu;
+                    H(i, k) -= d * u0;
+                    H(i, k + 1) -= d * u1;
+                    H(i, k + 2) -= d * u2;
+                }
+                if (k > l) {
+                    H(k + 1, k - 1) = 0.0;
+                    H(k + 2, k - 1) = 0.0;
+                }
+            }
+            x = H(k + 1, k);
+            y = H(k + 2, k);
+            if (k < hi - 2)
+                z = H(k + 3, k);
+        }
+        // final 2-vector reflector on rows / columns hi - 1, hi
+        {
+            const int k = hi - 1;
+            const double nrm = std::sqrt(x * x + y * y);
+            if (nrm != 0.0) {
+                const double beta = x > 0.0 ? -nrm : nrm;
+                const double u0 = x - beta, u1 = y;
+                const double uu = u0 * u0 + u1 * u1;
+                for (int j = k - 1; j <= hi; ++j) {
+                    const double d = 2.0 * (u0 * H(k, j) + u1 * H(k + 1, j)) / uu;
+                    H(k, j) -= d * u0;
+                    H(k + 1, j) -= d * u1;
+                }
+                for (int i = l; i <= hi; ++i) {
+                    const double d = 2.0 * (H(i, k) * u0 + H(i, k + 1) * u1) / uu;
+                    H(i, k) -= d * u0;
+                    H(i, k + 1) -= d * u1;
+                }
+                H(k + 1, k - 1) = 0.0;
+            }
+        }
+    }
+    return true;
+}
+
+// Cholesky G = R^T R (R upper, row-major) of a symmetric positive definite m x m matrix and the
+// inverse of R; false when a pivot is not positive.
+bool chol_upper_inverse(int m, const double *G, double *Rinv)
+{
+    std::vector<double> R((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        for (int j = i; j < m; ++j) {
+            double s = G[(size_t)i * m + j];
+            for (int k = 0; k < i; ++k)
+                s -= R[(size_t)k * m + i] * R[(size_t)k * m + j];
+            if (j == i) {
+                if (!(s > 0.0))
+                    return false;
+                R[(size_t)i * m + i] = std::sqrt(s);
+            } else {
+                R[(size_t)i * m + j] = s / R[(size_t)i * m + i];
+            }
+        }
+    }
+    // R^-1 by back substitution, column by column
+    for (int i = 0; i < m * m; ++i)
+        Rinv[i] = 0.0;
+    for (int j = 0; j < m; ++j) {
+        for (int i = j; i >= 0; --i) {
+            double s = (i == j) ? 1.0 : 0.0;
+            for (int k = i + 1; k <= j; ++k)
+                s -= R[(size_t)i * m + k] * Rinv[(size_t)k * m + j];
+            Rinv[(size_t)i * m + j] = s / R[(size_t)i * m + i];
+        }
+    }
+    return true;
+}
+
+template <typename T>
+mvgd_status eigs_impl(mvgd_matrix *L, const mvgd_eigs_params &p, double *lre, double *lim,
+                      mvgd_eigs_info *info, hipStream_t s)
+{
+    const int64_t n = L->n_total, ld = L->ld;
+    const int slots = L->K + 1;
+    const T *val = (const T *)L->ell_val;
+    const int32_t *col = L->ell_col;
+    const int nev = p.nev;
+    const int m = p.block > 0 ? p.block : std::min(kEigMaxBlock, std::max(nev + 8, 2 * nev));
+    // degree: fixed, or per iteration 2 sqrt((b - a)/(a - a0)) clamped to [8, 500], which makes the
+    // filter grow by about e^4 from a down to the bottom of the spectrum
+    int degree = p.degree;
+    const int max_iter = p.max_iter > 0 ? p.max_iter : 500;
+    const double tol = p.tol > 0.0 ? p.tol : 1e-10;
+    const int nblk_g = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+    const size_t blk = (size_t)n * m;
+    const int mm = m * m;
+    double *V, *X, *Y, *Z, *part, *gout, *rdev;
+    uint8_t *mask;
+    unsigned long long *gb;
+    auto carve = [&](Carver &cv) {
+        for (double **v : {&V, &X, &Y, &Z})
+            cv.take(*v, sizeof(double) * blk);
+        cv.take(part, sizeof(double) * (size_t)nblk_g * mm);
+        cv.take(gout, sizeof(double) * mm);
+        cv.take(rdev, sizeof(double) * mm);
+        cv.take(mask, (size_t)n);
+        cv.take(gb, sizeof(unsigned long long));
+    };
+    Carver sz;
+    carve(sz);
+    void *work = nullptr;
+    if (dev_alloc(&work, sz.off, s) != hipSuccess)
+        return fail(MVGD_ENOMEM, "device allocation failed (eigensolver work, %zu bytes)", sz.off);
+    struct Release {
+        void *w;
+        hipStream_t s;
+        ~Release() { (void)hipFreeAsync(w, s); }
+    } release_work{work, s};
+    Carver cv{(char *)work, 0};
+    carve(cv);
+    const unsigned nb1 = (unsigned)((n + kEigThreads - 1) / kEigThreads);
+    const unsigned nbr = (unsigned)((n + (kEigThreads / kWave) - 1) / (kEigThreads / kWave));
+    eig_mask_kernel<<<nb1, kEigThreads, 0, s>>>(L->perm, n, p.fixed, mask);
+    eig_init_kernel<<<(unsigned)((blk + kEigThreads - 1) / kEigThreads), kEigThreads, 0, s>>>(
+        n, m, mask, (unsigned long long)p.seed, Y);
+    (void)hipMemsetAsync(gb, 0, sizeof(unsigned long long), s);
+    eig_gersh_kernel<T><<<nb1, kEigThreads, 0, s>>>(val, n, ld, slots, mask, gb);
+    std::vector<double> G(mm), Rinv(mm), Hh(mm), re(m), im(m);
+    unsigned long long gb_host = 0;
+    // A^T B on the device, read back into `out`
+    auto gram = [&](const double *A, const double *B, std::vector<double> &out) -> bool {
+        eig_gram_kernel<<<nblk_g, kEigThreads, 0, s>>>(n, m, A, B, part);
+        eig_reduce_kernel<<<(unsigned)((mm + kEigThreads - 1) / kEigThreads), kEigThreads, 0, s>>>(
+            part, nblk_g, mm, gout);
+        return hipMemcpyAsync(out.data(), gout, sizeof(double) * mm, hipMemcpyDeviceToHost, s) ==
+                   hipSuccess &&
+               hipStreamSynchronize(s) == hipSuccess;
+    };
+    // dst = src R^-1 with G = src^T src = R^T R (a diagonal shift if G is not numerically positive)
+    auto cholqr = [&](const double *src, double *dst) -> mvgd_status {
+        if (!gram(src, src, G))
+            return fail(MVGD_EDEVICE, "eigensolver: Gram matrix read-back failed");
+        double tr = 0.0;
+        for (int i = 0; i < m; ++i)
+            tr += G[(size_t)i * m + i];
+        bool ok = chol_upper_inverse(m, G.data(), Rinv.data());
+        for (int t = 0; !ok && t < 4; ++t) {
+            for (int i = 0; i < m; ++i)
+                G[(size_t)i * m + i] += 1e-13 * std::pow(100.0, t) * tr;
+            ok = chol_upper_inverse(m, G.data(), Rinv.data());
+        }
+        if (!ok)
+            return fail(MVGD_EDEVICE, "eigensolver: the block lost rank (Cholesky QR failed)");
+        if (hipMemcpyAsync(rdev, Rinv.data(), sizeof(double) * mm, hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return fail(MVGD_EDEVICE, "eigensolver: upload failed");
+        eig_rmul_kernel<<<nbr, kEigThreads, 0, s>>>(n, m, src, rdev, dst);
+        return check_launch("eigensolver");
+    };
+    // V = orthonormal basis of Y (Cholesky QR twice, through X)
+    auto orth = [&]() -> mvgd_status {
+        if (mvgd_status st = cholqr(Y, X); st != MVGD_OK)
+            return st;
+        return cholqr(X, V);
+    };
+    // Ritz values of V^T A V, sorted by real part (then imaginary part)
+    std::vector<std::pair<double, double>> ritz(m), prev;
+    auto rayleigh_ritz = [&]() -> mvgd_status {
+        eig_cheb_kernel<T><<<nbr, kEigThreads, 0, s>>>(col, val, n, ld, slots, m, mask, nullptr, V, Z,
+                                                       1.0, 0.0, 0.0);
+        if (!gram(V, Z, Hh))
+            return fail(MVGD_EDEVICE, "eigensolver: Rayleigh quotient read-back failed");
+        if (!dense_eigvals(m, Hh.data(), re.data(), im.data()))
+            return fail(MVGD_EDEVICE, "eigensolver: the dense eigenvalue iteration did not converge");
+        for (int i = 0; i < m; ++i)
+            ritz[i] = {re[i], im[i]};
+        std::sort(ritz.begin(), ritz.end());
+        return MVGD_OK;
+    };
+    if (mvgd_status st = orth(); st != MVGD_OK)
+        return st;
+    if (hipMemcpyAsync(&gb_host, gb, sizeof gb_host, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(MVGD_EDEVICE, "eigensolver: spectrum bound read-back failed");
+    // decode the ordered encoding (positive values: the top bit set)
+    const double bound = gb_host ? __builtin_bit_cast(double, gb_host & 0x7fffffffffffffffull) : 0.0;
+    const double b = 1.01 * bound + 1e-300;
+    if (mvgd_status st = rayleigh_ritz(); st != MVGD_OK)
+        return st;
+    int it = 0, stable = 0;
+    double change = INFINITY;
+    for (; it < max_iter && stable < 2; ++it) {
+        // Chebyshev filter on [a, b], scaled by its value at a0 (Zhou-Saad recurrence)
+        const double a0 = std::min(ritz[0].first, 0.0);
+        double a = ritz[m - 1].first;
+        if (!(a > a0) || !(a < b))
+            a = 0.5 * (a0 + b);
+        const double e = 0.5 * (b - a), c = 0.5 * (b + a);
+        const double s1 = e / (a0 - c);
+        if (p.degree <= 0)
+            degree = (int)std::min(500.0, std::max(8.0, std::ceil(2.0 * std::sqrt((b - a) / std::max(a - a0, 1e-300 * b)))));
+        double sg = s1;
+        // Y = (s1 / e)(A V - c V)
+        eig_cheb_kernel<T><<<nbr, kEigThreads, 0, s>>>(col, val, n, ld, slots, m, mask, nullptr, V, Y,
+                                                       s1 / e, -c * s1 / e, 0.0);
+        const double *xp = V;
+        double *yp = Y, *zp = Z;
+        for (int k = 2; k <= degree; ++k) {
+            const double sn = 1.0 / (2.0 / s1 - sg);
+            eig_cheb_kernel<T><<<nbr, kEigThreads, 0, s>>>(col, val, n, ld, slots, m, mask, xp, yp, zp,
+                                                           2.0 * sn / e, -2.0 * sn * c / e, -sg * sn);
+            // rotate: x <- y, y <- z, z <- the free buffer
+            double *freebuf = (xp == V) ? X : (double *)xp;
+            xp = yp;
+            yp = zp;
+            zp = freebuf;
+            sg = sn;
+        }
+        if (mvgd_status st = check_launch("eigensolver"); st != MVGD_OK)
+            return st;
+        // the filtered block is in yp: orthonormalise into V (through the other buffers)
+        if (yp != Y) {
+            if (hipMemcpyAsync(Y, yp, sizeof(double) * blk, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(MVGD_EDEVICE, "eigensolver: copy failed");
+        }
+        if (mvgd_status st = orth(); st != MVGD_OK)
+            return st;
+        prev = ritz;
+        if (mvgd_status st = rayleigh_ritz(); st != MVGD_OK)
+            return st;
+        change = 0.0;
+        for (int i = 0; i < nev; ++i) {
+            const double d = std::hypot(ritz[i].first - prev[i].first, ritz[i].second - prev[i].second);
+            const double sc = std::max(1.0, std::hypot(ritz[i].first, ritz[i].second));
+            change = std::max(change, d / sc);
+        }
+        stable = change <= tol ? stable + 1 : 0;
+    }
+    for (int i = 0; i < nev; ++i) {
+        lre[i] = ritz[i].first;
+        lim[i] = ritz[i].second;
+    }
+    info->iterations = it;
+    info->converged = stable >= 2 ? 1 : 0;
+    info->block = m;
+    info->degree = degree;
+    info->spectrum_bound = bound;
+    info->max_change = change;
+    return MVGD_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -1221,6 +1589,40 @@ mvgd_status mvgd_timing(mvgd_matrix *L, mvgd_timing_t *t)
             return fail(MVGD_EDEVICE, "event timing failed");
         t->have_apply = 1;
     }
+    return MVGD_OK;
+}
+
+mvgd_status mvgd_eigs(mvgd_matrix *L, const mvgd_eigs_params *p, double *lambda_re,
+                      double *lambda_im, mvgd_eigs_info *info, void *stream)
+{
+    if (!L || !p || !lambda_re || !lambda_im || !info)
+        return fail(MVGD_EINVAL, "NULL argument");
+    if (p->nev < 1 || p->nev > kEigMaxBlock)
+        return fail(MVGD_EINVAL, "nev must be in [1, %d] (got %d)", kEigMaxBlock, p->nev);
+    if (p->block != 0 && (p->block < p->nev || p->block > kEigMaxBlock))
+        return fail(MVGD_EINVAL, "block must be 0 or in [nev, %d] (got %d)", kEigMaxBlock, p->block);
+    if (p->degree < 0 || p->degree > 1000 || p->max_iter < 0 || !(p->tol >= 0.0))
+        return fail(MVGD_EINVAL, "degree must be in [0, 1000], max_iter >= 0, tol >= 0");
+    const int m = p->block > 0 ? p->block : std::min(kEigMaxBlock, std::max(p->nev + 8, 2 * p->nev));
+    if (L->n_total <= m)
+        return fail(MVGD_EINVAL, "%lld rows; the block of %d vectors needs more",
+                    (long long)L->n_total, m);
+    memset(info, 0, sizeof *info);
+    if (p->fixed && !is_device_pointer(p->fixed, L->device))
+        return fail(MVGD_EINVAL, "fixed must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    L->stream = s;
+    if (L->precision == MVGD_FP64)
+        return eigs_impl<double>(L, *p, lambda_re, lambda_im, info, s);
+    return eigs_impl<float>(L, *p, lambda_re, lambda_im, info, s);
+}
+
+mvgd_status mvgd_dense_eigvals(int32_t m, const double *a, double *re, double *im)
+{
+    if (m < 1 || !a || !re || !im)
+        return fail(MVGD_EINVAL, "m must be positive and the arrays non-NULL");
+    if (!dense_eigvals(m, a, re, im))
+        return fail(MVGD_EINVAL, "the QR iteration did not converge");
     return MVGD_OK;
 }
 

@@ -25,7 +25,8 @@ MVGD_FLAG_LS, MVGD_FLAG_H_OVERRIDE, MVGD_FLAG_KEEP_DIAG, MVGD_FLAG_TIME = 1, 2, 
 MVGD_FLAG_MLS, MVGD_FLAG_DIVERGENCE = 16, 32
 
 EXPORTS = ("mvgd_assemble", "mvgd_apply", "mvgd_free", "mvgd_csr", "mvgd_row_diag", "mvgd_info",
-           "mvgd_timing", "mvgd_row_stats", "mvgd_solve", "mvgd_assemble_neumann",
+           "mvgd_timing", "mvgd_row_stats", "mvgd_solve", "mvgd_assemble_neumann", "mvgd_eigs",
+           "mvgd_dense_eigvals",
            "mvgd_pool_trim", "mvgd_status_str",
            "mvgd_last_error", "mvgd_version")
 
@@ -81,6 +82,18 @@ class mvgd_solve_params(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("fixed", ctypes.c_void_p)]
 
 
+class mvgd_eigs_params(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("fixed", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64)]
+
+
+class mvgd_eigs_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("spectrum_bound", ctypes.c_double), ("max_change", ctypes.c_double)]
+
+
 class mvgd_neumann_info(ctypes.Structure):
     _fields_ = [("n_interior", ctypes.c_int64), ("n_ghost", ctypes.c_int64)]
 
@@ -120,6 +133,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                           ctypes.POINTER(vp), vp, vp,
                                           ctypes.POINTER(mvgd_neumann_info)]
     lib.mvgd_assemble_neumann.restype = i32
+    lib.mvgd_eigs.argtypes = [vp, ctypes.POINTER(mvgd_eigs_params), vp, vp,
+                              ctypes.POINTER(mvgd_eigs_info), vp]
+    lib.mvgd_eigs.restype = i32
+    lib.mvgd_dense_eigvals.argtypes = [i32, vp, vp, vp]
+    lib.mvgd_dense_eigvals.restype = i32
     lib.mvgd_pool_trim.argtypes = [ctypes.c_size_t]
     lib.mvgd_pool_trim.restype = i32
     lib.mvgd_status_str.argtypes = [i32]
@@ -333,6 +351,39 @@ def mvgd_solve(L: Matrix, b: torch.Tensor, x: torch.Tensor | None = None, *,
                            ctypes.byref(prm), ctypes.byref(info), ctypes.c_void_p(_stream(stream))))
     return x, {"iterations": info.iterations, "converged": info.converged,
                "rel_residual": info.rel_residual}
+
+
+def mvgd_eigs(L: Matrix, nev: int, *, block: int = 0, degree: int = 0, max_iter: int = 0,
+              tol: float = 0.0, fixed: torch.Tensor | None = None, seed: int = 1, stream=None):
+    """The nev eigenvalues of -L with the smallest real parts (complex numpy array, sorted by
+    real part) and the iteration info; `fixed` (device bool/uint8 [n_rows]) removes rows."""
+    import numpy as np
+    if fixed is not None:
+        if fixed.shape != (L.n_rows,):
+            raise ValueError("fixed must have one entry per row")
+        fixed = fixed.to(torch.uint8).contiguous()
+    prm = mvgd_eigs_params(int(nev), int(block), int(degree), int(max_iter), float(tol),
+                           fixed.data_ptr() if fixed is not None else None, int(seed))
+    re = (ctypes.c_double * int(nev))()
+    im = (ctypes.c_double * int(nev))()
+    info = mvgd_eigs_info()
+    _check(_lib.mvgd_eigs(L.handle, ctypes.byref(prm), ctypes.cast(re, ctypes.c_void_p),
+                          ctypes.cast(im, ctypes.c_void_p), ctypes.byref(info),
+                          ctypes.c_void_p(_stream(stream))))
+    lam = np.array(re[:]) + 1j * np.array(im[:])
+    return lam, {f: getattr(info, f) for f, _ in mvgd_eigs_info._fields_}
+
+
+def mvgd_dense_eigvals(a):
+    """Eigenvalues of a real square matrix (host numpy array) by the library's dense routine."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be square")
+    m = a.shape[0]
+    re, im = np.empty(m), np.empty(m)
+    _check(_lib.mvgd_dense_eigvals(m, a.ctypes.data, re.ctypes.data, im.ctypes.data))
+    return re + 1j * im
 
 
 def mvgd_pool_trim(keep_bytes: int = 0):

@@ -140,3 +140,46 @@ def test_neumann_arguments_rejected_on_host(mv):
     assert call(mv.mvgd_params(4, 2, 20, mv.MVGD_FP64, 0, 0.0)) == mv.MVGD_EUNSUPPORTED
     assert call(mv.mvgd_params(3, 1, 6, mv.MVGD_FP64, 0, 0.0)) == mv.MVGD_EUNSUPPORTED
     assert call(mv.mvgd_params(3, 2, 4, mv.MVGD_FP64, 0, 0.0)) == mv.MVGD_EINVAL  # k too small
+
+
+def test_dense_eigvals_against_lapack_and_closed_forms(mv):
+    """The host step of mvgd_eigs (Hessenberg reduction + double-shift QR) against LAPACK's
+    eigenvalues on random, symmetric, Hessenberg and nearly defective matrices, and against closed
+    forms: a rotation block (e^{+-i t}) and a companion matrix with known roots."""
+    from scipy.optimize import linear_sum_assignment
+    rng = __import__("numpy").random.default_rng(0)
+    np = __import__("numpy")
+    for m in (1, 2, 3, 5, 8, 16, 33, 64):
+        for kind in range(4):
+            A = rng.standard_normal((m, m))
+            if kind == 1:
+                A = A + A.T
+            elif kind == 2:
+                A = np.triu(A, -1)
+            elif kind == 3:
+                A = np.diag(np.repeat(rng.standard_normal(m // 2 + 1), 2)[:m]) + \
+                    1e-3 * rng.standard_normal((m, m))
+            ev, ref = mv.mvgd_dense_eigvals(A), np.linalg.eigvals(A)
+            C = np.abs(ev[:, None] - ref[None, :])
+            r, c = linear_sum_assignment(C)
+            assert C[r, c].max() <= 1e-10 * max(1.0, np.abs(ref).max()), (m, kind)
+    t = 0.7
+    ev = mv.mvgd_dense_eigvals(np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]]))
+    assert np.allclose(np.sort_complex(ev), np.sort_complex(np.exp([-1j * t, 1j * t])), atol=1e-15)
+    roots = np.array([1.0, -2.0, 3.0, 0.5, -0.25])
+    coef = np.poly(roots)
+    comp = np.zeros((5, 5))
+    comp[0] = -coef[1:] / coef[0]
+    comp[1:, :-1] = np.eye(4)
+    ev = mv.mvgd_dense_eigvals(comp)
+    assert np.allclose(np.sort(ev.real), np.sort(roots), atol=1e-12) and np.abs(ev.imag).max() < 1e-12
+
+
+def test_eigs_arguments_rejected_on_host(mv):
+    lib = mv._lib
+    info = mv.mvgd_eigs_info()
+    re = (ctypes.c_double * 4)()
+    im = (ctypes.c_double * 4)()
+    prm = mv.mvgd_eigs_params(4, 0, 0, 0, 0.0, None, 1)
+    assert lib.mvgd_eigs(None, ctypes.byref(prm), re, im, ctypes.byref(info), None) == -1
+    assert lib.mvgd_dense_eigvals(0, None, None, None) == -1

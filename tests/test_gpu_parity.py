@@ -880,6 +880,91 @@ def test_neumann_hemisphere_solve(mv, precision):
     L.free()
 
 
+# ----------------------------------------------------------------------------------------------
+# eigenvalues (Sec. 4: -Delta nu = lambda nu)
+# ----------------------------------------------------------------------------------------------
+def _dense_minus_L(rp, c, v, keep):
+    import scipy.sparse as sp
+    n = len(rp) - 1
+    A = -sp.csr_matrix((v, c, rp), shape=(n, n)).toarray()
+    return A[np.ix_(keep, keep)]
+
+
+def _match(got, ref):
+    """Largest distance between the two eigenvalue lists after an optimal pairing."""
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(got[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(C)
+    return C[r, c].max()
+
+
+def _closed_form(levels, mult):
+    return np.concatenate([np.full(mult(l), lam) for l, lam in levels])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_eigs_sphere(mv, precision):
+    """The 16 eigenvalues of -L with the smallest real parts on a 2,000-point sphere: against the
+    dense eigenvalues of the exported matrix (LAPACK), and near l (l + 1) with multiplicity
+    2 l + 1 (l = 0..3)."""
+    cl = clouds.sphere(2000, 1, 20)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    L = mv.mvgd_assemble(torch.tensor(cl.points, dtype=dt, device=DEV), 20)
+    lam, info = mv.mvgd_eigs(L, 16, tol=1e-11)
+    assert info["converged"] == 1, info
+    rp, c, v = _export_csr(mv, L, 2000, 20)
+    ev = np.linalg.eigvals(_dense_minus_L(rp, c, v, np.arange(2000)))
+    ref = ev[np.argsort(ev.real)][:16]
+    err = _match(lam, ref)
+    assert err <= 1e-8 * np.abs(ref).max(), (err, lam, ref)
+    exact = _closed_form([(0, 0.0), (1, 2.0), (2, 6.0), (3, 12.0)], lambda l: 2 * l + 1)
+    rel = np.abs(np.sort(lam.real) - exact)[1:] / exact[1:]
+    assert abs(lam.real[0]) < 1e-6 and rel.max() < 0.02, (lam, rel)
+    print(f"\n[eigs sphere 2k {precision}] {info}, |GPU - LAPACK| {err:.2e}, "
+          f"max rel err vs l(l+1) {rel.max():.2e}, max |imag| {np.abs(lam.imag).max():.1e}")
+    L.free()
+
+
+def test_eigs_hemisphere_dirichlet_and_neumann(mv):
+    """Open upper hemisphere: with the boundary points removed (Dirichlet) the spectrum is near
+    n (n + 1) with multiplicity n; on the Neumann handle with its ghost rows removed it is near
+    n (n - 1) with multiplicity n. Both against LAPACK on the same submatrices."""
+    cl = clouds.hemisphere(2000, 8, 20)
+    m = cl.meta["boundary"]
+    P = torch.tensor(cl.points, device=DEV)
+    # Dirichlet
+    L = mv.mvgd_assemble(P, 20)
+    lam, info = mv.mvgd_eigs(L, 10, tol=1e-11, fixed=torch.tensor(m, device=DEV))
+    assert info["converged"] == 1, info
+    rp, c, v = _export_csr(mv, L, cl.n_points, 20)
+    ev = np.linalg.eigvals(_dense_minus_L(rp, c, v, np.nonzero(~m)[0]))
+    ref = ev[np.argsort(ev.real)][:10]
+    err = _match(lam, ref)
+    assert err <= 1e-8 * np.abs(ref).max(), (err, lam, ref)
+    exact = _closed_form([(1, 2.0), (2, 6.0), (3, 12.0), (4, 20.0)], lambda l: l)
+    rel = np.abs(np.sort(lam.real) - exact) / exact
+    assert rel.max() < 0.03, (lam, rel)
+    print(f"\n[eigs hemisphere Dirichlet] {info}, |GPU - LAPACK| {err:.2e}, rel err {rel.max():.2e}")
+    L.free()
+    # Neumann
+    L, ni, gx, gs = mv.mvgd_assemble_neumann(P, torch.tensor(m, device=DEV), 20, 6)
+    ng = gs.shape[0]
+    ghost = torch.zeros(ni + ng, dtype=torch.uint8, device=DEV)
+    ghost[ni:] = 1
+    lam, info = mv.mvgd_eigs(L, 10, tol=1e-11, fixed=ghost)
+    assert info["converged"] == 1, info
+    rp, c, v = _export_csr(mv, L, ni + ng, 20)
+    ev = np.linalg.eigvals(_dense_minus_L(rp, c, v, np.arange(ni)))
+    ref = ev[np.argsort(ev.real)][:10]
+    err = _match(lam, ref)
+    assert err <= 1e-8 * np.abs(ref).max(), (err, lam, ref)
+    exact = _closed_form([(1, 0.0), (2, 2.0), (3, 6.0), (4, 12.0)], lambda l: l)
+    rel = np.abs(np.sort(lam.real) - exact)[1:] / exact[1:]
+    assert abs(lam.real[0]) < 1e-6 and rel.max() < 0.03, (lam, rel)
+    print(f"\n[eigs hemisphere Neumann] {info}, |GPU - LAPACK| {err:.2e}, rel err {rel.max():.2e}")
+    L.free()
+
+
 def test_neumann_rejects_too_few_boundary_points(mv):
     """k_boundary larger than the number of boundary points is an argument error, and leaves no
     handle."""
