@@ -275,6 +275,44 @@ def bench_neumann(args):
     print(json.dumps(out))
 
 
+def bench_eigs(args):
+    """Eigenvalues of -L on a random unit sphere (Sec. 4): the 16 with the smallest real parts by
+    the device's Chebyshev-filtered subspace iteration, FP32-mixed and FP64 matrices; errors
+    against l (l + 1) as the paper's E_l^inf (l = 1, 2, 3). Prints one JSON line."""
+    import torch
+    from paper_1603_04100_amd import clouds, mvgd as mv
+    n, k = args.eig_points, 20
+    cl = clouds.sphere(n, 5, k)
+    print(f"[bench] sphere eigenvalues: N={n} K={k}", file=sys.stderr, flush=True)
+    exact = np.concatenate([np.full(2 * l + 1, l * (l + 1.0)) for l in range(4)])
+    res = {}
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        P = torch.tensor(cl.points, dtype=dt, device="cuda:0")
+        L = mv.mvgd_assemble(P, k)
+        mv.mvgd_eigs(L, 4, max_iter=2)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, info = mv.mvgd_eigs(L, 16, tol=1e-10)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        lr = np.sort(lam.real)
+        einf = {f"E{l}_inf": float(np.max(np.abs(lr[l * l:(l + 1) ** 2] - l * (l + 1.0)))
+                                    / (l * (l + 1.0))) for l in (1, 2, 3)}
+        res[prec] = {"seconds": dt_s, "lambda": [float(x) for x in lr], "max_imag":
+                     float(np.abs(lam.imag).max()), **einf, **info}
+        print(f"[bench] {prec}: {dt_s:.3f} s, {info}, {einf}", file=sys.stderr, flush=True)
+        mv.mvgd_free(L)
+    out = {"metric": "seconds for the 16 smallest eigenvalues of -L on the sphere",
+           "value": res["fp32"]["seconds"], "unit": "s", "n_gpus": 1,
+           "steps": res["fp32"]["iterations"], "warmup": 1,
+           "ms_per_step": 1e3 * res["fp32"]["seconds"] / max(res["fp32"]["iterations"], 1),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 matrix/f64 vectors", "data": "synthetic",
+           "config": {"workload": "sphere_eigs", "n_points": n, "k": k, "nev": 16, "tol": 1e-10},
+           "results": res, "kernel_source_hash": kernel_source_hash()}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +327,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--solve-points", type=int, default=1_000_000)
+    ap.add_argument("--eig-points", type=int, default=200_000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy per step (counter scaling reference)")
     args = ap.parse_args()
@@ -306,6 +345,8 @@ def main():
         return bench_solve(args)
     if args.workload == "hemisphere_neumann":
         return bench_neumann(args)
+    if args.workload == "sphere_eigs":
+        return bench_eigs(args)
     cl = make_workload(args.workload)
     n, k = cl.n_points, cl.k
     batched = cl.offsets.shape[0] > 2

@@ -1486,6 +1486,8 @@ mvgd_status eigs_impl(mvgd_matrix *L, const mvgd_eigs_params &p, double *lre, do
     double change = INFINITY;
     for (; it < max_iter && stable < 2; ++it) {
         // Chebyshev filter on [a, b], scaled by its value at a0 (Zhou-Saad recurrence)
+        // unwanted interval [a, b]: a is the block's largest Ritz value (a lower cut, e.g. halfway
+        // into the block, took 1.6 times as many iterations at 200k points on the sphere)
         const double a0 = std::min(ritz[0].first, 0.0);
         double a = ritz[m - 1].first;
         if (!(a > a0) || !(a < b))

@@ -6,7 +6,7 @@
 // unwanted interval [a, b] and grows fast below a, is applied with the three-term recurrence, one
 // multi-column ELL product per degree; the block is then orthonormalised (Cholesky QR, twice) and
 // the Rayleigh quotient H = V^T A V (m x m) gives the Ritz values. b bounds the spectrum
-// (Gershgorin: the largest absolute row sum), a is the largest Ritz value of the previous step.
+// (Gershgorin: the largest absolute row sum), a the largest Ritz value of the previous step.
 // Rows flagged in `mask` are removed from the operator: the block is kept zero there, so the
 // iteration runs on the submatrix of the other rows and columns (Dirichlet points, ghost rows).
 //
