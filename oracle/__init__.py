@@ -230,6 +230,24 @@ def solve(row_ptr, cols, vals, b, sigma: float = 0.0, pinned=()):
     return spla.spsolve(A.tocsc(), np.asarray(b, dtype=np.float64))
 
 
+def eigenvalues(row_ptr, cols, vals, nev: int, keep=None):
+    """The nev eigenvalues of -L with the smallest real parts (Sec. 4: -Delta nu = lambda nu),
+    sorted by real part, with L the CSR matrix restricted to the rows and columns in `keep` (all by
+    default; removing boundary points gives the Dirichlet problem, removing ghost rows the
+    Neumann one). Dense eigenvalues of the nonsymmetric matrix (LAPACK via numpy) as the one
+    library step."""
+    import scipy.sparse as sp
+    n = len(row_ptr) - 1
+    A = -sp.csr_matrix((np.asarray(vals, dtype=np.float64), np.asarray(cols),
+                        np.asarray(row_ptr)), shape=(n, n)).toarray()
+    if keep is not None:
+        keep = np.asarray(keep)
+        A = A[np.ix_(keep, keep)]
+    ev = np.linalg.eigvals(A)
+    order = np.lexsort((ev.imag, ev.real))
+    return ev[order][:nev]
+
+
 def neumann_ghosts(points, boundary, k: int, k_boundary: int):
     """Ghost points of the reflection method for the Neumann condition on an open surface in R^3
     (Sec. 3.1), step by step:

@@ -671,3 +671,36 @@ def test_neumann_rows_sum_to_zero_and_converge(oracle_mod):
         x = oracle_mod.solve(rp, c, v, 7.0 * z ** 2 - 2.0, sigma=1.0)
         errs.append(np.abs(x - z ** 2).max())
     assert errs[0] < 5e-3 and errs[0] / errs[1] > 3.0, errs
+
+
+# ----------------------------------------------------------------------------------------------
+# eigenvalues (Sec. 4: -Delta nu = lambda nu)
+# ----------------------------------------------------------------------------------------------
+def test_eigenvalues_match_the_closed_form_spectra(oracle_mod):
+    """Unit sphere: l (l + 1) with multiplicity 2 l + 1; upper hemisphere with the boundary points
+    removed (Dirichlet): n (n + 1) with multiplicity n; with the reflection ghosts folded
+    (Neumann): n (n - 1) with multiplicity n. At 2,000 points the smallest eigenvalues of the
+    oracle's matrices lie within 2-3% of them, and the error falls when the sampling refines."""
+    def spectrum(levels, mult):
+        return np.concatenate([np.full(mult(l), lam) for l, lam in levels])
+
+    errs = []
+    for n in (1000, 2000):
+        P = clouds.sphere(n, 1, 20).points
+        rp, c, v = oracle_mod.assemble(P, 20)
+        lam = oracle_mod.eigenvalues(rp, c, v, 16)
+        exact = spectrum([(0, 0.0), (1, 2.0), (2, 6.0), (3, 12.0)], lambda l: 2 * l + 1)
+        assert abs(lam[0]) < 1e-8
+        errs.append((np.abs(np.sort(lam.real) - exact)[1:] / exact[1:]).max())
+    assert errs[1] < 0.02 and errs[1] < errs[0], errs
+    cl = clouds.hemisphere(2000, 8, 20)
+    m = cl.meta["boundary"]
+    rp, c, v = oracle_mod.assemble(cl.points, 20)
+    lam = oracle_mod.eigenvalues(rp, c, v, 10, keep=np.nonzero(~m)[0])
+    exact = spectrum([(1, 2.0), (2, 6.0), (3, 12.0), (4, 20.0)], lambda l: l)
+    assert (np.abs(np.sort(lam.real) - exact) / exact).max() < 0.03
+    rp, c, v, g = oracle_mod.neumann_rows(cl.points, m, 20, 6)
+    lam = oracle_mod.eigenvalues(rp, c, v, 10)
+    exact = spectrum([(1, 0.0), (2, 2.0), (3, 6.0), (4, 12.0)], lambda l: l)
+    assert abs(lam[0]) < 1e-8
+    assert (np.abs(np.sort(lam.real) - exact)[1:] / exact[1:]).max() < 0.03
