@@ -1795,6 +1795,44 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
         P.row_flags[q] = slow_row ? 2 : 0;
 }
 
+// The search's list of row q (original indices in ELL slots 1..K) in ascending original index,
+// mapped to sorted positions, into list[k][lane]: a bitonic network on KP >= K registers (padding
+// sorts last), fully unrolled, so every compare-exchange is a min and a max.
+template <int KP>
+__device__ __forceinline__ void sort_list(const AsmParams &P, int q, int qidx, int lane,
+                                          int32_t *list)
+{
+    const int K = P.K;
+    int v[KP];
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        int idx = 0x7fffffff;
+        if (k < K) {
+            idx = P.ell_col[(int64_t)(k + 1) * P.ld + q];
+            idx = (idx >= 0 && (int64_t)idx < P.n_rows) ? idx : qidx;
+        }
+        v[k] = idx;
+    }
+#pragma unroll
+    for (int size = 2; size <= KP; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1)
+#pragma unroll
+            for (int i = 0; i < KP; ++i) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const int lo = min(v[i], v[j]), hi = max(v[i], v[j]);
+                    const bool up = (i & size) == 0;
+                    v[i] = up ? lo : hi;
+                    v[j] = up ? hi : lo;
+                }
+            }
+#pragma unroll
+    for (int k = 0; k < KP; ++k)
+        if (k < K)
+            list[k * kWave + lane] = P.iperm[v[k]];
+}
+
 // Per-lane fit of one row (one wave per 64 consecutive rows in cell order): the neighbour list
 // of the search (original indices in ELL slots 1..K) is put in canonical order, ascending
 // original index (the order of the rows of V in the paper's normal equations), mapped back to
@@ -1820,24 +1858,15 @@ __global__ __launch_bounds__(64) MVGD_FIT_ATTR void fit_kernel(AsmParams P)
         return;
     const int q = (int)q64;
     const int K = P.K;
-    const int64_t ld = P.ld;
     const int qidx = P.perm[q];
-    for (int k = 0; k < K; ++k) {
-        const int idx = P.ell_col[(int64_t)(k + 1) * ld + q];
-        list[k * kWave + lane] = (idx >= 0 && (int64_t)idx < P.n_rows) ? idx : qidx;
-    }
-    for (int a = 1; a < K; ++a) {
-        const int v = list[a * kWave + lane];
-        int b = a - 1;
-        while (b >= 0 && list[b * kWave + lane] > v) {
-            list[(b + 1) * kWave + lane] = list[b * kWave + lane];
-            --b;
-        }
-        list[(b + 1) * kWave + lane] = v;
-    }
-#pragma unroll 4
-    for (int k = 0; k < K; ++k)
-        list[k * kWave + lane] = P.iperm[list[k * kWave + lane]];
+    if (K <= 8)
+        sort_list<8>(P, q, qidx, lane, list);
+    else if (K <= 16)
+        sort_list<16>(P, q, qidx, lane, list);
+    else if (K <= 32)
+        sort_list<32>(P, q, qidx, lane, list);
+    else
+        sort_list<64>(P, q, qidx, lane, list);
     const Pt<T> *spts = (const Pt<T> *)P.spts;
     const bool slow_row = P.row_flags ? (P.row_flags[q] & 2) != 0 : false;
     fit_row<T, NA, D>(P, spts, list, lane, q, spts[q], slow_row);
