@@ -89,12 +89,12 @@ enum {
 };
 
 enum {
-    MVGD_SEARCH_DEFAULT = 0, /* TILE for MVGD_FP32_MIXED, GROUP for MVGD_FP64 */
+    MVGD_SEARCH_DEFAULT = 0, /* TILE */
     MVGD_SEARCH_GROUP = 1, /* the 64 queries of a group stream their common cell box via LDS */
     MVGD_SEARCH_LANE = 2,  /* every query walks the cells of its own box */
     MVGD_SEARCH_TILE = 3   /* as GROUP, with the 64 x 64 query-candidate squared distances of each
-                              staged chunk formed on the matrix cores (MVGD_FP32_MIXED only;
-                              MVGD_EUNSUPPORTED for MVGD_FP64) */
+                              staged chunk formed on the matrix cores (FP32 operands from the
+                              centred coordinates; the selection stays exact in both precisions) */
 };
 
 typedef struct {

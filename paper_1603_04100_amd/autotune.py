@@ -7,7 +7,7 @@ The tunables change only performance, never results (the neighbour search is exa
 * cells_per_point  cell-table budget per point (finer grids cost a larger table)
 * launch           1 = one workgroup per 64-point group, 2 = persistent per-XCD work queues
 * search           1 = the group's queries stream their common cell box, 2 = every query walks
-                   its own box, 3 = as 1 with the distances from the matrix cores (float points)
+                   its own box, 3 = as 1 with the distances from the matrix cores
 
 ``tune`` times the assembly kernel (HIP events recorded by the library on its stream) over a
 grid of settings on a given workload and returns the fastest. ``main`` tunes the named
@@ -31,7 +31,7 @@ GRID = {
     "radius_mu": (1.4, 1.7, 2.0),
     "cells_per_point": (4.0, 8.0, 16.0),
     "launch": (1, 2),
-    "search": (1, 2),
+    "search": (1, 2, 3),
 }
 
 _table = None
@@ -119,10 +119,7 @@ def main():
             P = torch.tensor(cl.points.astype(np.float32 if prec == "fp32" else np.float64),
                              device="cuda:0")
             d = cl.meta.get("d", 2)
-            grid = dict(GRID)
-            if prec == "fp32":
-                grid["search"] = GRID["search"] + (3,)
-            best, res = tune(P, cl.k, cloud_offsets=offs, reps=args.reps, d_manifold=d, grid=grid)
+            best, res = tune(P, cl.k, cloud_offsets=offs, reps=args.reps, d_manifold=d)
             default_ms = next(ms for ms, s in res if s == {"cell_alpha": 0.6, "radius_mu": 1.7,
                                                            "cells_per_point": 8.0, "launch": 1,
                                                            "search": 1})

@@ -73,7 +73,10 @@ static_assert(kBinWords * kWave * 4 <= kBndCap * kWave * 8, "histogram must fit 
 constexpr int kTileStage = 6 * kWave * 4 + 2 * kWave * 4;
 __host__ __device__ constexpr int search_stage_bytes(int pt_bytes, int S)
 {
-    return S == 2 ? kTileStage : kWave * pt_bytes + 2 * kWave * 4;
+    // the tile search's exhaustive fallback streams through the group staging in the same area
+    return S == 2 ? (kTileStage > kWave * pt_bytes + 2 * kWave * 4 ? kTileStage
+                                                                   : kWave * pt_bytes + 2 * kWave * 4)
+                  : kWave * pt_bytes + 2 * kWave * 4;
 }
 
 // LDS of one search wave (S: 0 group, 1 lane, 2 tile): histogram / boundary keys and indices,
@@ -235,10 +238,10 @@ __device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g
 }
 
 // ---------------------------------------------------------------------------------------------
-// tile search (float points): squared distances of a 64-query x 64-candidate tile on the
-// matrix cores
+// tile search: squared distances of a 64-query x 64-candidate tile on the matrix cores
 // ---------------------------------------------------------------------------------------------
-// About a centre c (a query of the sub-group), with q^ = q - c and p^ = p - c rounded to FP32,
+// About a centre c (a query of the sub-group), with q^ = q - c and p^ = p - c formed in the
+// points' precision and rounded once to FP32 (float or double points alike),
 //   g(q, p) = |q^|^2 + (1 + kTileAdd) |p^|^2 - 2 q^ . p^
 // is one dot product of the augmented vectors (-2 q^, 1, |q^|^2) and (p^, (1 + kTileAdd)|p^|^2, 1),
 // six terms, formed by three v_mfma_f32_32x32x2f32 per 32 x 32 block. Its error against the
@@ -268,15 +271,15 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // 32 qb + l % 32). Staged entries past the end of the stream get g ~ 3e38 (never selected: every
 // threshold is at most 1e38) and original index 0x7fffffff.
 // Staged sorted positions and original indices are in st_pos / st_idx for the consumer.
-template <int NA, typename F>
+template <typename T, int NA, typename F>
 __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &g, const int bmin[3],
                                            const int bmax[3], char *lds_rng, char *lds_stage,
-                                           const float cq[4], const float (&bq)[2][3], int qmask,
+                                           const T cq[4], const float (&bq)[2][3], int qmask,
                                            F &&consume)
 {
     const int lane = lane_id();
     const int hl = lane >> 5, ll = lane & 31;
-    const Pt<float> *spts = (const Pt<float> *)P.spts;
+    const Pt<T> *spts = (const Pt<T> *)P.spts;
     int32_t *rng_start = (int32_t *)lds_rng;
     int32_t *rng_pref = rng_start + kWave;
     float *st_aug = (float *)lds_stage;
@@ -302,7 +305,7 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
         }
     };
     // the point of stream slot tt of the current cell batch (ranges in LDS), or none
-    auto load_point = [&](int tt, int total, Pt<float> &p, int32_t &pos, int32_t &idx) {
+    auto load_point = [&](int tt, int total, Pt<T> &p, int32_t &pos, int32_t &idx) {
         pos = -1;
         idx = 0x7fffffff;
         if (tt < total) {
@@ -334,7 +337,7 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
         rng_start[lane] = (int32_t)st;
         rng_pref[lane] = incl - (int)cn;
         __syncthreads();
-        Pt<float> p_n = {{0.f, 0.f, 0.f, 0.f}};
+        Pt<T> p_n = {{(T)0, (T)0, (T)0, (T)0}};
         int32_t pos_n, idx_n;
         load_point(lane, total, p_n, pos_n, idx_n);
         for (int sb = 0; sb < total; sb += kWave) {
@@ -343,7 +346,7 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
                 float np = 0.f;
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    av[a] = p_n.v[a] - cq[a];
+                    av[a] = (float)(p_n.v[a] - cq[a]); // centred in T, rounded once to FP32
                     np = fmaf(av[a], av[a], np);
                 }
                 av[4] = np * (1.f + kTileAdd);
@@ -1213,7 +1216,6 @@ __device__ __forceinline__ void search_lane(const AsmParams &P, const CloudGrid 
 template <typename T, int NA, int S>
 __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t group, char *lds)
 {
-    static_assert(S != 2 || sizeof(T) == 4, "the tile search is for float points");
     const int lane = lane_id();
     const int K = P.K;
     char *lds_rng = lds + kLdsSearch;
@@ -1362,24 +1364,25 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                 bool force_slow = false;
                 int nbox_lo[3], nbox_hi[3];
                 if constexpr (S == 2) {
-                    // ===== tile search: g(query, candidate) from the matrix cores (float points) =====
+                    // ===== tile search: g(query, candidate) from the matrix cores =====================
                     // Histograms of 32 bins x 32-bit counters per query: bin b holds the g with
                     // round(g sb) = b (half-integer edges), sb ~ 31.5 / cut of the query's own cut;
                     // values past the cut go to a 33rd, uncounted row (the boundary index area,
                     // unused until pass 2). The bin is read from the bits of fma(g, sb, 2^23).
                     const int hl = lane >> 5, ll = lane & 31;
                     constexpr int NB = kTileBins;
-                    int32_t *cnt_in = (int32_t *)(lds_stage + kTileStage + kWave * 8);
+                    int32_t *cnt_in =
+                        (int32_t *)(lds_stage + search_stage_bytes((int)sizeof(Pt<T>), S) + kWave * 8);
                     int32_t *cnt_bd = cnt_in + kWave;
                     // centre: the peel's first query; query operands (-2 q^, 1, |q^|^2)
-                    float cq[4];
+                    T cq[4];
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
                         cq[a] = __shfl(qp.v[a], c_lane, kWave);
                     float qh[4], nq = 0.f;
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
-                        qh[a] = qp.v[a] - cq[a];
+                        qh[a] = (float)(qp.v[a] - cq[a]);
                         nq = fmaf(qh[a], qh[a], nq);
                     }
                     float *qaug = (float *)lds_stage; // the candidate operand area, free between streams
@@ -1427,7 +1430,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                             hist[w * kWave + lane] = 0u;
                         __syncthreads();
                         const float sb0 = __shfl(sb, ll, kWave), sb1 = __shfl(sb, 32 + ll, kWave);
-                        n_streamed += stream_tile<NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq, qmask,
+                        n_streamed += stream_tile<T, NA>(P, g, box_lo, box_hi, lds_rng, lds_stage, cq, bq, qmask,
                             [&](int cb, int qb, const floatx16 &acc) {
                                 const float s_ = qb ? sb1 : sb0;
                                 char *h = (char *)(hist + 32 * qb + ll);
@@ -1499,7 +1502,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                         const int rb0 = __shfl(b0, ll, kWave), rb1 = __shfl(b0, 32 + ll, kWave);
                         const float bl0 = __shfl(base_lo, ll, kWave), bl1 = __shfl(base_lo, 32 + ll, kWave);
                         const float s10 = __shfl(s1, ll, kWave), s11 = __shfl(s1, 32 + ll, kWave);
-                        n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
+                        n_streamed += stream_tile<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
                             [&](int cb, int qb, const floatx16 &acc) {
                                 const float s_ = qb ? sq1 : sq0, bl_ = qb ? bl1 : bl0, s1_ = qb ? s11 : s10;
                                 const uint32_t own = (uint32_t)(qb ? rb1 : rb0) * kWave * 4;
@@ -1542,7 +1545,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     const float hc0 = __shfl(hic, ll, kWave), hc1 = __shfl(hic, 32 + ll, kWave);
                     const float lc0 = __shfl(loc, ll, kWave), lc1 = __shfl(loc, 32 + ll, kWave);
                     const int qi0 = __shfl(qidx, ll, kWave), qi1 = __shfl(qidx, 32 + ll, kWave);
-                    Pt<float> qq0, qq1;
+                    Pt<T> qq0, qq1;
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
                         qq0.v[a] = __shfl(qp.v[a], ll, kWave);
@@ -1550,7 +1553,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     }
                     const int32_t *st_pos = (const int32_t *)(lds_stage + 6 * kWave * 4);
                     const int32_t *st_idx = st_pos + kWave;
-                    n_streamed += stream_tile<NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
+                    n_streamed += stream_tile<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
                         [&](int cb, int qb, const floatx16 &acc) {
                             const float hc = qb ? hc1 : hc0, lc = qb ? lc1 : lc0;
                             uint32_t mh = 0, ms = 0; // hits (g <= hic) and sure ones (g < loc), bit r
@@ -1576,7 +1579,7 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                                     const int slot = atomicAdd(&cnt_bd[jb], 1);
                                     if (slot < kBndCap) {
                                         bndkey[slot * kWave + jb] =
-                                            exact_key<float, NA>(qb ? qq1 : qq0, spts[st_pos[ci]]);
+                                            exact_key<T, NA>(qb ? qq1 : qq0, spts[st_pos[ci]]);
                                         bndpos[slot * kWave + jb] = idx;
                                     }
                                 }

@@ -274,29 +274,25 @@ void *staging(size_t bytes)
 std::atomic<int> g_occupancy[2][3][3]; // [double][n - 2][search mode]
 std::atomic<int> g_n_cu{0};
 
-// Persistent search kernel of a mode (0 group, 1 lane, 2 tile; tile only for float points).
+// Persistent search kernel of a mode (0 group, 1 lane, 2 tile).
 template <typename T, int NA>
 const void *search_kernel_ptr(int smode)
 {
-    if constexpr (sizeof(T) == 4)
-        if (smode == 2)
-            return (const void *)search_persistent_kernel<T, NA, 2>;
-    return smode == 1 ? (const void *)search_persistent_kernel<T, NA, 1>
-                      : (const void *)search_persistent_kernel<T, NA, 0>;
+    return smode == 2   ? (const void *)search_persistent_kernel<T, NA, 2>
+           : smode == 1 ? (const void *)search_persistent_kernel<T, NA, 1>
+                        : (const void *)search_persistent_kernel<T, NA, 0>;
 }
 
 template <typename T, int NA>
 void launch_search(int smode, bool persistent, unsigned nblk, size_t lds, hipStream_t stream,
                    const AsmParams &ap)
 {
-    if constexpr (sizeof(T) == 4) {
-        if (smode == 2) {
-            if (persistent)
-                search_persistent_kernel<T, NA, 2><<<nblk, kWave, lds, stream>>>(ap);
-            else
-                search_kernel<T, NA, 2><<<nblk, kWave, lds, stream>>>(ap);
-            return;
-        }
+    if (smode == 2) {
+        if (persistent)
+            search_persistent_kernel<T, NA, 2><<<nblk, kWave, lds, stream>>>(ap);
+        else
+            search_kernel<T, NA, 2><<<nblk, kWave, lds, stream>>>(ap);
+        return;
     }
     if (persistent && smode == 1)
         search_persistent_kernel<T, NA, 1><<<nblk, kWave, lds, stream>>>(ap);
@@ -557,12 +553,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     ap.counters = L->counters;
     ap.queue = d_queue;
     const int d = p.d_manifold;
-    // search mode: 0 group, 1 lane, 2 tile (float points only; rejected for FP64 by validate).
-    // The default is the tile search for float points and the group search for doubles.
-    const int smode = p.search == MVGD_SEARCH_LANE   ? 1
-                      : p.search == MVGD_SEARCH_TILE ? 2
-                      : p.search == MVGD_SEARCH_GROUP ? 0
-                                                      : (sizeof(T) == 4 ? 2 : 0);
+    // search mode: 0 group, 1 lane, 2 tile (the default)
+    const int smode = p.search == MVGD_SEARCH_LANE ? 1 : p.search == MVGD_SEARCH_GROUP ? 0 : 2;
     const size_t lds = (size_t)search_lds_bytes((int)sizeof(Pt<T>), smode);
     const bool persistent = p.launch == MVGD_LAUNCH_PERSISTENT;
     unsigned nblk = (unsigned)(ap.groups_per_xcd * 8);
@@ -651,8 +643,6 @@ mvgd_status validate(const void *points, int64_t n_total, const int64_t *cloud_o
         return fail(MVGD_EINVAL, "unknown launch mode %d", p->launch);
     if (p->search < MVGD_SEARCH_DEFAULT || p->search > MVGD_SEARCH_TILE)
         return fail(MVGD_EINVAL, "unknown search mode %d", p->search);
-    if (p->search == MVGD_SEARCH_TILE && p->precision == MVGD_FP64)
-        return fail(MVGD_EUNSUPPORTED, "the tile search is for MVGD_FP32_MIXED points");
     if (p->cell_alpha < 0.0f || p->radius_mu < 0.0f || p->cells_per_point < 0.0f ||
         !std::isfinite(p->cell_alpha) || !std::isfinite(p->radius_mu) ||
         !std::isfinite(p->cells_per_point) || (p->cells_per_point > 0.0f && p->cells_per_point < 0.25f) ||

@@ -74,13 +74,6 @@ def test_invalid_parameters_rejected_on_host(mv, field, value, status):
     assert mv._lib.mvgd_last_error()
 
 
-def test_tile_search_is_for_fp32(mv):
-    p = mv.mvgd_params(3, 2, 20, mv.MVGD_FP64, 0, 0.0)
-    p.search = mv.MVGD_SEARCH_TILE
-    st, h = _call(mv, p)
-    assert st == mv.MVGD_EUNSUPPORTED and h is None
-
-
 @pytest.mark.parametrize("n_amb,d,k,flags", [
     (4, 1, 6, 0),      # curves live in R^2 or R^3
     (3, 1, 1, 0),      # K >= 2 for the three monomials of a curve

@@ -593,12 +593,14 @@ def test_flat_torus_1m_sampled(mv, precision):
     _sampled(mv, clouds.flat_torus4(1_000_000, 4, 32), precision, n_rows=400)
 
 
-@pytest.mark.parametrize("name", ["flat_torus4_1m", "torus_200k", "ellipsoids_256"])
+@pytest.mark.parametrize("name", ["flat_torus4_1m", "torus_200k", "ellipsoids_256",
+                                  "flat_torus4_1m-fp64"])
 def test_tile_search_full_size_equals_group(mv, name):
     """At the benchmark sizes the tile search gives the group search's matrix bit for bit (the
     group search is compared with the oracle above)."""
+    name, _, prec = name.partition("-")
     cl = clouds.config(name)
-    P = torch.tensor(cl.points.astype(np.float32), device=DEV)
+    P = torch.tensor(cl.points.astype(np.float64 if prec == "fp64" else np.float32), device=DEV)
     offs = [int(v) for v in cl.offsets] if cl.offsets.shape[0] > 2 else None
     res = []
     for search in (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_TILE):
@@ -707,10 +709,10 @@ def _lattice_with_ties():
                                   "batch-fp32", "sphere2d-fp32"])
 def test_search_modes_agree(mv, case):
     """The per-lane search (every query walks its own cell box), the group search (64 queries
-    stream their common box) and, for float points, the tile search (the group search with the
-    query-candidate distances from the matrix cores) select the same neighbours and give
-    bit-identical matrices, on clouds with exact ties, duplicates, curves, planar clouds and
-    batches; and the oracle agrees on the sets."""
+    stream their common box) and the tile search (the group search with the query-candidate
+    distances from the matrix cores) select the same neighbours and give bit-identical matrices,
+    in both precisions, on clouds with exact ties, duplicates, curves, planar clouds and batches;
+    and the oracle agrees on the sets."""
     name, precision = case.split("-")
     d, offs, k = 2, None, 20
     if name == "flat4":
@@ -734,9 +736,7 @@ def test_search_modes_agree(mv, case):
     dt = torch.float64 if precision == "fp64" else torch.float32
     P = torch.tensor(pts, dtype=dt, device=DEV)
     out = []
-    modes = (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_LANE)
-    if precision == "fp32":
-        modes += (mv.MVGD_SEARCH_TILE,)
+    modes = (mv.MVGD_SEARCH_GROUP, mv.MVGD_SEARCH_LANE, mv.MVGD_SEARCH_TILE)
     for search in modes:
         for launch in (1, 2):
             L = mv.mvgd_assemble(P, k, cloud_offsets=offs, d_manifold=d,
