@@ -442,6 +442,10 @@ __device__ __forceinline__ void jacobi_eig(double A[N][N], double W[N][N])
         const bool done = !(off > 1e-34 * dia);
         if (__ballot(!done) == 0)
             break;
+        // a converged lane takes no further rotation: its result does not depend on how long the
+        // other lanes of its wave iterate (the same row gives the same bits in any batch)
+        if (done)
+            continue;
 #pragma unroll
         for (int p = 0; p < N; ++p) {
 #pragma unroll

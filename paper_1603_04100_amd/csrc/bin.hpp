@@ -1,6 +1,7 @@
 // bin.hpp -- counting sort of the points into Morton-ordered cells (the neighbour-search grid).
 //
-// bbox_kernel      per-cloud bounding box over all ambient coordinates + non-finite count
+// bbox_kernel      partial bounding boxes (ambient and projected coordinates) + non-finite counts
+// bbox_reduce_kernel  the per-cloud box from the partials
 // plan_kernel      per-cloud cell grid and Morton part tables from the bounding boxes
 // key_kernel       cell key of every point and its slot inside the cell (atomic count)
 // scan_*           exclusive prefix sum of the cell counts -> cell start offsets
@@ -44,10 +45,13 @@ __global__ void stats_init_kernel(CloudStats *st, int n_clouds, unsigned long lo
     st[c].nonfinite = 0;
 }
 
+// Per-block partial bounding boxes: part[(cloud * gridDim.x + block) * 16 + a], a < 7 the minima
+// (ambient, then projected), 7 + a the maxima, 14 the count of non-finite points (as a double).
+// bbox_reduce_kernel folds them per cloud (no contended atomics).
 template <typename T, int NA>
 __global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts,
                                                    const int64_t *__restrict__ offsets, Proj pr,
-                                                   CloudStats *st)
+                                                   double *__restrict__ part)
 {
     const int c = blockIdx.y;
     const int64_t b = offsets[c], e = offsets[c + 1];
@@ -58,29 +62,41 @@ __global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts,
         mx[a] = -INFINITY;
     }
     unsigned long long bad = 0;
-    for (int64_t i = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < e;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        T x[NA];
-        bool fin = true;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // four points per trip, their loads issued together
+    for (int64_t i0 = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < e; i0 += 4 * stride) {
+        T xs[4][NA];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            x[a] = pts[i * NA + a];
-            fin = fin && isfinite((double)x[a]);
-        }
-        if (!fin) {
-            ++bad;
-            continue;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + u * stride;
+#pragma unroll
+            for (int a = 0; a < NA; ++a)
+                xs[u][a] = i < e ? pts[i * NA + a] : (T)0;
         }
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-            mn[a] = fmin(mn[a], (double)x[a]);
-            mx[a] = fmax(mx[a], (double)x[a]);
-        }
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u * stride >= e)
+                break;
+            const T *x = xs[u];
+            bool fin = true;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double u = (double)project<T, NA>(x, pr, a);
-            mn[4 + a] = fmin(mn[4 + a], u);
-            mx[4 + a] = fmax(mx[4 + a], u);
+            for (int a = 0; a < NA; ++a)
+                fin = fin && isfinite((double)x[a]);
+            if (!fin) {
+                ++bad;
+                continue;
+            }
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                mn[a] = fmin(mn[a], (double)x[a]);
+                mx[a] = fmax(mx[a], (double)x[a]);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double pu = (double)project<T, NA>(x, pr, a);
+                mn[4 + a] = fmin(mn[4 + a], pu);
+                mx[4 + a] = fmax(mx[4 + a], pu);
+            }
         }
     }
     __shared__ double smn[4][7], smx[4][7];
@@ -100,29 +116,89 @@ __global__ __launch_bounds__(256) void bbox_kernel(const T *__restrict__ pts,
         sbad[w] = bad;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = blockDim.x / kWave;
+    if (threadIdx.x < 15) {
+        const int a = (int)threadIdx.x, nw = blockDim.x / kWave;
+        double v;
+        if (a < 7) {
+            v = smn[0][a];
+            for (int k = 1; k < nw; ++k)
+                v = fmin(v, smn[k][a]);
+        } else if (a < 14) {
+            v = smx[0][a - 7];
+            for (int k = 1; k < nw; ++k)
+                v = fmax(v, smx[k][a - 7]);
+        } else {
+            unsigned long long tb = 0;
+            for (int k = 0; k < nw; ++k)
+                tb += sbad[k];
+            v = (double)tb;
+        }
+        part[((int64_t)c * gridDim.x + blockIdx.x) * 16 + a] = v;
+    }
+}
+
+// One block per cloud: folds the nb partial boxes of the cloud into its statistics.
+template <int NA>
+__global__ __launch_bounds__(256) void bbox_reduce_kernel(const double *__restrict__ part, int nb,
+                                                          CloudStats *st)
+{
+    const int c = blockIdx.x;
+    double mn[7], mx[7], bad = 0.0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+        mn[a] = INFINITY;
+        mx[a] = -INFINITY;
+    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const double *p = part + ((int64_t)c * nb + b) * 16;
+#pragma unroll
         for (int a = 0; a < 7; ++a) {
-            if (a >= NA && a < 4)
-                continue;
-            double lo = smn[0][a], hi = smx[0][a];
-            for (int k = 1; k < nw; ++k) {
-                lo = fmin(lo, smn[k][a]);
-                hi = fmax(hi, smx[k][a]);
-            }
-            if (lo <= hi) {
-                unsigned long long *pmn = a < 4 ? &st[c].mn[a] : &st[c].pmn[a - 4];
-                unsigned long long *pmx = a < 4 ? &st[c].mx[a] : &st[c].pmx[a - 4];
-                atomicMin(pmn, ord_encode(lo));
-                atomicMax(pmx, ord_encode(hi));
+            mn[a] = fmin(mn[a], p[a]);
+            mx[a] = fmax(mx[a], p[7 + a]);
+        }
+        bad += p[14];
+    }
+    __shared__ double smn[4][7], smx[4][7], sbad[4];
+    const int w = threadIdx.x / kWave, l = lane_id();
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+        mn[a] = seg_min(mn[a], kWave);
+        mx[a] = seg_max(mx[a], kWave);
+    }
+    bad = wave_sum(bad);
+    if (l == 0) {
+        for (int a = 0; a < 7; ++a) {
+            smn[w][a] = mn[a];
+            smx[w][a] = mx[a];
+        }
+        sbad[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    const int nw = blockDim.x / kWave;
+    for (int a = 0; a < 7; ++a) {
+        if (a >= NA && a < 4)
+            continue;
+        double lo = smn[0][a], hi = smx[0][a];
+        for (int k = 1; k < nw; ++k) {
+            lo = fmin(lo, smn[k][a]);
+            hi = fmax(hi, smx[k][a]);
+        }
+        if (lo <= hi) {
+            if (a < 4) {
+                st[c].mn[a] = ord_encode(lo);
+                st[c].mx[a] = ord_encode(hi);
+            } else {
+                st[c].pmn[a - 4] = ord_encode(lo);
+                st[c].pmx[a - 4] = ord_encode(hi);
             }
         }
-        unsigned long long tb = 0;
-        for (int k = 0; k < nw; ++k)
-            tb += sbad[k];
-        if (tb)
-            atomicAdd(&st[c].nonfinite, tb);
     }
+    double tb = 0.0;
+    for (int k = 0; k < nw; ++k)
+        tb += sbad[k];
+    st[c].nonfinite = (unsigned long long)tb;
 }
 
 template <typename T, int NA>

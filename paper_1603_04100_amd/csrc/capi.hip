@@ -393,6 +393,9 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     };
     int64_t *d_meta;
     CloudStats *d_stats;
+    double *d_bpart;
+    // bounding boxes: blocks per cloud, each writing a partial box (folded by one block per cloud)
+    const int bbx = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (max_n + 1023) / 1024));
     uint32_t *d_parts, *d_counts, *d_start, *d_keys, *d_slots;
     unsigned int *d_queue;
     int32_t *d_iperm, *d_perm_tmp;
@@ -401,6 +404,7 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     auto carve_scratch = [&](Carver &cv) {
         cv.take(d_meta, sizeof(int64_t) * n_meta);
         cv.take(d_stats, sizeof(CloudStats) * n_clouds);
+        cv.take(d_bpart, sizeof(double) * 16 * (size_t)bbx * (size_t)n_clouds);
         cv.take(d_parts, sizeof(uint32_t) * part_total);
         cv.take(d_counts, sizeof(uint32_t) * cell_total);
         cv.take(d_start, sizeof(uint32_t) * (cell_total + 1));
@@ -453,13 +457,16 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         d_stats, n_clouds, L->counters, d_queue);
     const Proj proj = binning_projection(n_amb);
     {
-        const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(512, (max_n + 2047) / 2048));
-        if (n_amb == 2)
-            bbox_kernel<T, 2><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
-        else if (n_amb == 3)
-            bbox_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
-        else
-            bbox_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_stats);
+        if (n_amb == 2) {
+            bbox_kernel<T, 2><<<dim3(bbx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_bpart);
+            bbox_reduce_kernel<2><<<n_clouds, 256, 0, stream>>>(d_bpart, bbx, d_stats);
+        } else if (n_amb == 3) {
+            bbox_kernel<T, 3><<<dim3(bbx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_bpart);
+            bbox_reduce_kernel<3><<<n_clouds, 256, 0, stream>>>(d_bpart, bbx, d_stats);
+        } else {
+            bbox_kernel<T, 4><<<dim3(bbx, n_clouds), 256, 0, stream>>>(points, d_meta, proj, d_bpart);
+            bbox_reduce_kernel<4><<<n_clouds, 256, 0, stream>>>(d_bpart, bbx, d_stats);
+        }
     }
     {
         PlanArgs pa;
