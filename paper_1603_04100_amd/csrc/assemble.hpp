@@ -1295,8 +1295,10 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
             int cells = 1;
     #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                const double umn = seg_min(in ? (double)uq[ax] : INFINITY, kWave);
-                const double umx = seg_max(in ? (double)uq[ax] : -INFINITY, kWave);
+                // minima and maxima are exact in the points' precision (half the shuffles of a
+                // double reduction for float points)
+                const double umn = (double)seg_min(in ? uq[ax] : (T)INFINITY, kWave);
+                const double umx = (double)seg_max(in ? uq[ax] : (T)-INFINITY, kWave);
                 const double slack = 0.01 * g.cell + 1e-6 * (fabs(umn) + fabs(umx));
                 lo_[ax] = uniform(cell_coord<double>(umn - R - slack, g.lo[ax], g.inv_cell, g.dim[ax]));
                 hi_[ax] = uniform(cell_coord<double>(umx + R + slack, g.lo[ax], g.inv_cell, g.dim[ax]));
@@ -1844,16 +1846,18 @@ __device__ __forceinline__ void sort_list(const AsmParams &P, int q, int qidx, i
 // of the search (original indices in ELL slots 1..K) is put in canonical order, ascending
 // original index (the order of the rows of V in the paper's normal equations), mapped back to
 // sorted positions for local gathers, and fitted (fit_row writes the finished ELL row).
-// Occupancy target of the fit kernel: 4 waves per SIMD (128 VGPRs) runs the R^4 fit ~11% faster
-// than the compiler's 148 VGPRs (measured at 1M points); the R^3 fit fits in 111 VGPRs anyway.
+// Occupancy target of the fit kernel (waves per SIMD): float points 4 (128 VGPRs; the R^4 fit
+// ~11% faster than the compiler's 148), double points 3 (at 128 VGPRs the FP64 fit spills enough
+// to run 40% slower). Measured at 1M points in R^4.
 #ifndef MVGD_FIT_WAVES_PER_EU
 #define MVGD_FIT_WAVES_PER_EU 4
 #endif
-#if MVGD_FIT_WAVES_PER_EU > 0
-#define MVGD_FIT_ATTR __attribute__((amdgpu_waves_per_eu(MVGD_FIT_WAVES_PER_EU)))
-#else
-#define MVGD_FIT_ATTR
+#ifndef MVGD_FIT_WAVES_PER_EU_FP64
+#define MVGD_FIT_WAVES_PER_EU_FP64 3
 #endif
+#define MVGD_FIT_ATTR                                                                             \
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? MVGD_FIT_WAVES_PER_EU_FP64                \
+                                                      : MVGD_FIT_WAVES_PER_EU)))
 template <typename T, int NA, int D>
 __global__ __launch_bounds__(64) MVGD_FIT_ATTR void fit_kernel(AsmParams P)
 {

@@ -917,6 +917,23 @@ def test_eigs_sphere(mv, precision):
     L.free()
 
 
+def test_eigs_parameters(mv):
+    """Explicit block, fixed degree and a looser tolerance find the same bottom of the spectrum;
+    out-of-range parameters are argument errors."""
+    cl = clouds.sphere(2000, 1, 20)
+    L = mv.mvgd_assemble(torch.tensor(cl.points, device=DEV), 20)
+    lam, info = mv.mvgd_eigs(L, 4, block=12, degree=16, tol=1e-9)
+    assert info["converged"] == 1 and info["block"] == 12 and info["degree"] == 16, info
+    ref = oracle.eigenvalues(*oracle.assemble(cl.points, 20), 4)
+    assert _match(lam, ref) <= 1e-6 * np.abs(ref).max(), (lam, ref)
+    for kw in ({"nev": 0}, {"nev": 65}, {"nev": 8, "block": 4}, {"nev": 4, "degree": -1}):
+        nev = kw.pop("nev")
+        with pytest.raises(mv.MvgdError) as e:
+            mv.mvgd_eigs(L, nev, **kw)
+        assert e.value.status == mv.MVGD_EINVAL
+    L.free()
+
+
 def test_eigs_hemisphere_dirichlet_and_neumann(mv):
     """Open upper hemisphere (FP64): with the boundary points removed (Dirichlet) and on the
     Neumann handle with its ghost rows removed, against the oracle's eigenvalues of the same
