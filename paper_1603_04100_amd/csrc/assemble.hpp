@@ -80,13 +80,12 @@ __host__ __device__ constexpr int search_stage_bytes(int pt_bytes, int S)
 }
 
 // LDS of one search wave (S: 0 group, 1 lane, 2 tile): histogram / boundary keys and indices,
-// plus (group and tile search) the cell ranges, the staging, the sub-group worklist and (tile)
-// the per-query sure / boundary counters
+// plus (group and tile search) the cell ranges, the staging and the sub-group worklist
 __host__ __device__ constexpr int search_lds_bytes(int pt_bytes, int S)
 {
     return kLdsSearch + (S == 1 ? 0
                                 : 2 * kWave * 4 /*cell ranges*/ + search_stage_bytes(pt_bytes, S) +
-                                      kWave * 8 /*worklist*/ + (S == 2 ? 2 * kWave * 4 : 0));
+                                      kWave * 8 /*worklist*/);
 }
 
 // LDS of one fit wave: the neighbour list [K][64]
@@ -1377,9 +1376,6 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     // unused until pass 2). The bin is read from the bits of fma(g, sb, 2^23).
                     const int hl = lane >> 5, ll = lane & 31;
                     constexpr int NB = kTileBins;
-                    int32_t *cnt_in =
-                        (int32_t *)(lds_stage + search_stage_bytes((int)sizeof(Pt<T>), S) + kWave * 8);
-                    int32_t *cnt_bd = cnt_in + kWave;
                     // centre: the peel's first query; query operands (-2 q^, 1, |q^|^2)
                     T cq[4];
 #pragma unroll
@@ -1545,20 +1541,17 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     const float hic = act ? f32_up((kb2 * kTileU1 + kTileU0 * nqd) * (1.0 + 1e-6)) : -INFINITY;
                     const double lo_k = ((lo_e - kTileU0 * nqd) / kTileU1) * (1.0 - ed) - E * nqd;
                     const float loc = act ? f32_down(lo_k - 1e-6 * fabs(lo_k)) : -INFINITY;
-                    cnt_in[lane] = 0;
-                    cnt_bd[lane] = 0;
-                    __syncthreads();
                     const float hc0 = __shfl(hic, ll, kWave), hc1 = __shfl(hic, 32 + ll, kWave);
                     const float lc0 = __shfl(loc, ll, kWave), lc1 = __shfl(loc, 32 + ll, kWave);
                     const int qi0 = __shfl(qidx, ll, kWave), qi1 = __shfl(qidx, 32 + ll, kWave);
-                    Pt<T> qq0, qq1;
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        qq0.v[a] = __shfl(qp.v[a], ll, kWave);
-                        qq1.v[a] = __shfl(qp.v[a], 32 + ll, kWave);
-                    }
                     const int32_t *st_pos = (const int32_t *)(lds_stage + 6 * kWave * 4);
                     const int32_t *st_idx = st_pos + kWave;
+                    // a boundary entry's sorted position waits in the low word of its key slot until
+                    // the key is computed after the stream
+                    int32_t *bnd_at = (int32_t *)bndkey;
+                    // sure / boundary counts of queries ll (c*0) and 32 + ll (c*1); the two lanes of
+                    // a query (one per candidate half) hold the same totals
+                    int cin0 = 0, cin1 = 0, cbd0 = 0, cbd1 = 0;
                     n_streamed += stream_tile<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
                         [&](int cb, int qb, const floatx16 &acc) {
                             const float hc = qb ? hc1 : hc0, lc = qb ? lc1 : lc0;
@@ -1568,32 +1561,69 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                                 mh |= (acc[r] <= hc ? 1u : 0u) << r;
                                 ms |= (acc[r] < lc ? 1u : 0u) << r;
                             }
+                            if (__ballot(mh != 0) == 0)
+                                return;
+                            // drop the query itself (and padding): original indices of this lane's
+                            // candidates, four runs of four
                             const int qi = qb ? qi1 : qi0;
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int4 v = *(const int4 *)(st_idx + 32 * cb + 8 * j + 4 * hl);
+                                const uint32_t drop = (v.x == qi || v.x == 0x7fffffff ? 1u : 0u) |
+                                                      (v.y == qi || v.y == 0x7fffffff ? 2u : 0u) |
+                                                      (v.z == qi || v.z == 0x7fffffff ? 4u : 0u) |
+                                                      (v.w == qi || v.w == 0x7fffffff ? 8u : 0u);
+                                mh &= ~(drop << (4 * j));
+                            }
+                            uint32_t mS = mh & ms, mB = mh & ~ms;
+                            // slots: the lower candidate half of a block first, then the upper
+                            const int c = __popc(mS) | (__popc(mB) << 16);
+                            const int pc = __shfl_xor(c, 32, kWave);
+                            const int ci0 = qb ? cin1 : cin0, cb0 = qb ? cbd1 : cbd0;
+                            int sS = ci0 + (hl ? (pc & 0xffff) : 0);
+                            int sB = cb0 + (hl ? (pc >> 16) : 0);
+                            const int ci1 = ci0 + (c & 0xffff) + (pc & 0xffff);
+                            const int cb1 = cb0 + (c >> 16) + (pc >> 16);
+                            if (qb) {
+                                cin1 = ci1;
+                                cbd1 = cb1;
+                            } else {
+                                cin0 = ci1;
+                                cbd0 = cb1;
+                            }
                             const int jb = 32 * qb + ll;
-                            while (mh != 0) {
-                                const int r = __builtin_ctz(mh);
-                                mh &= mh - 1;
-                                const int ci = 32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3);
-                                const int idx = st_idx[ci];
-                                if (idx == qi || idx == 0x7fffffff)
-                                    continue;
-                                if ((ms >> r) & 1u) {
-                                    const int slot = atomicAdd(&cnt_in[jb], 1);
-                                    if (slot < K)
-                                        P.ell_col[(int64_t)(slot + 1) * ls + s0 + jb] = idx;
-                                } else {
-                                    const int slot = atomicAdd(&cnt_bd[jb], 1);
-                                    if (slot < kBndCap) {
-                                        bndkey[slot * kWave + jb] =
-                                            exact_key<T, NA>(qb ? qq1 : qq0, spts[st_pos[ci]]);
-                                        bndpos[slot * kWave + jb] = idx;
-                                    }
+                            int32_t *col = P.ell_col + (int64_t)ls + s0 + jb;
+                            while (mS != 0) {
+                                const int r = __builtin_ctz(mS);
+                                mS &= mS - 1;
+                                if (sS < K)
+                                    col[(int64_t)sS * ls] = st_idx[32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3)];
+                                ++sS;
+                            }
+                            while (mB != 0) {
+                                const int r = __builtin_ctz(mB);
+                                mB &= mB - 1;
+                                if (sB < kBndCap) {
+                                    const int ci = 32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3);
+                                    bnd_at[2 * (sB * kWave + jb)] = st_pos[ci];
+                                    bndpos[sB * kWave + jb] = st_idx[ci];
                                 }
+                                ++sB;
                             }
                         });
                     __syncthreads();
-                    nin = cnt_in[lane];
-                    nb = cnt_bd[lane];
+                    nin = hl ? cin1 : cin0;
+                    nb = hl ? cbd1 : cbd0;
+                    // exact keys of the boundary entries (two point loads in flight)
+                    if (act && nb <= kBndCap) {
+                        for (int bi = 0; bi < nb; bi += 2) {
+                            const Pt<T> c0 = spts[bnd_at[2 * (bi * kWave + lane)]];
+                            const Pt<T> c1 = spts[bnd_at[2 * (min(bi + 1, nb - 1) * kWave + lane)]];
+                            bndkey[bi * kWave + lane] = exact_key<T, NA>(qp, c0);
+                            if (bi + 1 < nb)
+                                bndkey[(bi + 1) * kWave + lane] = exact_key<T, NA>(qp, c1);
+                        }
+                    }
                     keep_s = 0;
                     lo_s = 0.f;
                     hi_s = f32_up(kb2 * (1.0 + 3.0 * ed));
