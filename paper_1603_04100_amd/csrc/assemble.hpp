@@ -147,6 +147,24 @@ __device__ __forceinline__ float cull_dist<double, 4>(const Pt<double> &q, const
 }
 
 // Stream every point of the cell box [bmin, bmax] of cloud g through LDS, 64 at a time, and call
+// The cell of a batch (its lane) that holds stream slot tt < total: the last cell whose first slot
+// is at most tt (an empty cell shares its first slot with the next one, so the last such cell is
+// never empty). Two levels: the first slots of cells 8, 16, ..., 56 (wave-uniform, p8[1..7]) pick
+// a run of eight cells, whose first slots are then read from LDS together.
+__device__ __forceinline__ int slot_cell(int tt, const int (&p8)[8], const int32_t *rng_pref)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i)
+        c += p8[i] <= tt ? 1 : 0;
+    const int4 a = *(const int4 *)(rng_pref + 8 * c);
+    const int4 b = *(const int4 *)(rng_pref + 8 * c + 4);
+    const int f = (a.y <= tt ? 1 : 0) + (a.z <= tt ? 1 : 0) + (a.w <= tt ? 1 : 0) +
+                  (b.x <= tt ? 1 : 0) + (b.y <= tt ? 1 : 0) + (b.z <= tt ? 1 : 0) +
+                  (b.w <= tt ? 1 : 0);
+    return 8 * c + f;
+}
+
 // visit(f, point, sorted position, original index) on every lane for every point, where f is the
 // culling distance of the point to the lane's query (+inf for inactive lanes and for the query
 // itself). Staged entries past the end of the stream are sentinels (position -1, coordinates
@@ -185,18 +203,15 @@ __device__ __forceinline__ int stream_box(const AsmParams &P, const CloudGrid &g
         streamed += total;
         rng_start[lane] = (int32_t)st;
         rng_pref[lane] = incl - (int)cn;
+        int p8[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            p8[i] = __builtin_amdgcn_readlane(incl - (int)cn, 8 * i);
         __syncthreads();
         for (int sb = 0; sb < total; sb += kWave) {
             const int tt = sb + lane;
             if (tt < total) {
-                int lo = 0, hi = kWave - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (rng_pref[mid] <= tt)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
+                const int lo = slot_cell(tt, p8, rng_pref);
                 const int pos = rng_start[lo] + (tt - rng_pref[lo]);
                 st_pt[lane] = spts[pos];
                 st_pos[lane] = pos;
@@ -303,19 +318,13 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
             cn = P.cell_start[cell + 1] - st;
         }
     };
+    int p8[8]; // first slots of cells 8 i of the current batch
     // the point of stream slot tt of the current cell batch (ranges in LDS), or none
     auto load_point = [&](int tt, int total, Pt<T> &p, int32_t &pos, int32_t &idx) {
         pos = -1;
         idx = 0x7fffffff;
         if (tt < total) {
-            int lo = 0, hi = kWave - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (rng_pref[mid] <= tt)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
+            const int lo = slot_cell(tt, p8, rng_pref);
             pos = rng_start[lo] + (tt - rng_pref[lo]);
             p = spts[pos];
             idx = P.perm[pos];
@@ -335,6 +344,9 @@ __device__ __forceinline__ int stream_tile(const AsmParams &P, const CloudGrid &
         streamed += total;
         rng_start[lane] = (int32_t)st;
         rng_pref[lane] = incl - (int)cn;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            p8[i] = __builtin_amdgcn_readlane(incl - (int)cn, 8 * i);
         __syncthreads();
         Pt<T> p_n = {{(T)0, (T)0, (T)0, (T)0}};
         int32_t pos_n, idx_n;
