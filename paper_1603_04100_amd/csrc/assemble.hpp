@@ -1561,9 +1561,16 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                     // a boundary entry's sorted position waits in the low word of its key slot until
                     // the key is computed after the stream
                     int32_t *bnd_at = (int32_t *)bndkey;
-                    // sure / boundary counts of queries ll (c*0) and 32 + ll (c*1); the two lanes of
-                    // a query (one per candidate half) hold the same totals
+                    // Sure entries take rows 0..K of the query's ELL column in arrival order (row 0
+                    // belongs to the row's own entry and is rewritten by the fit). The query itself
+                    // takes a row like any sure entry but is not written there; after the stream the
+                    // entry of row 0 moves into that row (or, the query not being a sure entry, to the
+                    // end of the list), so that rows 1..nin hold the sure neighbours.
+                    // Per query block (queries ll and 32 + ll; the two lanes of a query, one per
+                    // candidate half, hold the same totals): sure and boundary counts, the row the
+                    // query itself took (-1: none) and the entry written to row 0 (-1: none).
                     int cin0 = 0, cin1 = 0, cbd0 = 0, cbd1 = 0;
+                    int srow0 = -1, srow1 = -1, rz0 = -1, rz1 = -1;
                     n_streamed += stream_tile<T, NA>(P, g, nbox_lo, nbox_hi, lds_rng, lds_stage, cq, bq, qmask,
                         [&](int cb, int qb, const floatx16 &acc) {
                             const float hc = qb ? hc1 : hc0, lc = qb ? lc1 : lc0;
@@ -1573,20 +1580,9 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                                 mh |= (acc[r] <= hc ? 1u : 0u) << r;
                                 ms |= (acc[r] < lc ? 1u : 0u) << r;
                             }
+                            // (padding entries, g ~ 3e38, never pass hic <= 1e38)
                             if (__ballot(mh != 0) == 0)
                                 return;
-                            // drop the query itself (and padding): original indices of this lane's
-                            // candidates, four runs of four
-                            const int qi = qb ? qi1 : qi0;
-#pragma unroll
-                            for (int j = 0; j < 4; ++j) {
-                                const int4 v = *(const int4 *)(st_idx + 32 * cb + 8 * j + 4 * hl);
-                                const uint32_t drop = (v.x == qi || v.x == 0x7fffffff ? 1u : 0u) |
-                                                      (v.y == qi || v.y == 0x7fffffff ? 2u : 0u) |
-                                                      (v.z == qi || v.z == 0x7fffffff ? 4u : 0u) |
-                                                      (v.w == qi || v.w == 0x7fffffff ? 8u : 0u);
-                                mh &= ~(drop << (4 * j));
-                            }
                             uint32_t mS = mh & ms, mB = mh & ~ms;
                             // slots: the lower candidate half of a block first, then the upper
                             const int c = __popc(mS) | (__popc(mB) << 16);
@@ -1604,13 +1600,25 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                                 cbd0 = cb1;
                             }
                             const int jb = 32 * qb + ll;
-                            int32_t *col = P.ell_col + (int64_t)ls + s0 + jb;
+                            const int qi = qb ? qi1 : qi0;
+                            int32_t *col = P.ell_col + s0 + jb;
+                            int srow = -1, rz = -1;
                             while (mS != 0) {
                                 const int r = __builtin_ctz(mS);
                                 mS &= mS - 1;
-                                if (sS < K)
-                                    col[(int64_t)sS * ls] = st_idx[32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3)];
+                                const int idx = st_idx[32 * cb + 8 * (r >> 2) + 4 * hl + (r & 3)];
+                                if (sS <= K && idx != qi)
+                                    col[(int64_t)sS * ls] = idx;
+                                srow = idx == qi ? sS : srow;
+                                rz = sS == 0 ? idx : rz;
                                 ++sS;
+                            }
+                            if (qb) {
+                                srow1 = max(srow1, srow);
+                                rz1 = max(rz1, rz);
+                            } else {
+                                srow0 = max(srow0, srow);
+                                rz0 = max(rz0, rz);
                             }
                             while (mB != 0) {
                                 const int r = __builtin_ctz(mB);
@@ -1624,10 +1632,37 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                             }
                         });
                     __syncthreads();
-                    nin = hl ? cin1 : cin0;
-                    nb = hl ? cbd1 : cbd0;
-                    // exact keys of the boundary entries (two point loads in flight)
+                    {
+                        // the other half's records of this lane's query (its block hl)
+                        const int psrow = __shfl_xor(hl ? srow0 : srow1, 32, kWave);
+                        const int prz = __shfl_xor(hl ? rz0 : rz1, 32, kWave);
+                        const int srow = max(hl ? srow1 : srow0, psrow);
+                        const int rz = max(hl ? rz1 : rz0, prz);
+                        const int nall = hl ? cin1 : cin0;
+                        nin = srow >= 0 ? nall - 1 : nall;
+                        nb = hl ? cbd1 : cbd0;
+                        if (act && nall <= K) {
+                            int32_t *col = P.ell_col + s0 + lane;
+                            if (srow > 0)
+                                col[(int64_t)srow * ls] = rz;
+                            else if (srow < 0 && nall > 0)
+                                col[(int64_t)nall * ls] = rz;
+                        }
+                    }
+                    // exact keys of the boundary entries (the query itself dropped; two point loads in
+                    // flight)
                     if (act && nb <= kBndCap) {
+                        int m = 0;
+                        for (int bi = 0; bi < nb; ++bi) {
+                            const int id = bndpos[bi * kWave + lane];
+                            const int at = bnd_at[2 * (bi * kWave + lane)];
+                            if (id != qidx) {
+                                bndpos[m * kWave + lane] = id;
+                                bnd_at[2 * (m * kWave + lane)] = at;
+                                ++m;
+                            }
+                        }
+                        nb = m;
                         for (int bi = 0; bi < nb; bi += 2) {
                             const Pt<T> c0 = spts[bnd_at[2 * (bi * kWave + lane)]];
                             const Pt<T> c1 = spts[bnd_at[2 * (min(bi + 1, nb - 1) * kWave + lane)]];
