@@ -1816,16 +1816,22 @@ __device__ __forceinline__ void search_group(const AsmParams &P, const int64_t g
                 const int r = K - nin;
                 const bool slow = act && (force_slow || nb > kBndCap || nb < r || nin >= K);
                 // ----- resolve the boundary by exact (key, index) rank --------------------------------
+                // (every key slot is read once into registers; slots past nb are masked)
                 if (act && !slow) {
+                    double kk[kBndCap];
+                    int pp[kBndCap];
+#pragma unroll
+                    for (int j = 0; j < kBndCap; ++j) {
+                        kk[j] = bndkey[j * kWave + lane];
+                        pp[j] = bndpos[j * kWave + lane];
+                    }
                     for (int bi = 0; bi < nb; ++bi) {
                         const double kb = bndkey[bi * kWave + lane];
                         const int pb = bndpos[bi * kWave + lane]; // original index
                         int rank = 0;
-                        for (int bj = 0; bj < nb; ++bj) {
-                            const double kj = bndkey[bj * kWave + lane];
-                            if (kj < kb || (kj == kb && bndpos[bj * kWave + lane] < pb))
-                                ++rank;
-                        }
+#pragma unroll
+                        for (int bj = 0; bj < kBndCap; ++bj)
+                            rank += (bj < nb && (kk[bj] < kb || (kk[bj] == kb && pp[bj] < pb))) ? 1 : 0;
                         if (rank < r)
                             lst[(nin + rank) * ls] = pb;
                     }
