@@ -201,46 +201,76 @@ __global__ __launch_bounds__(256) void bbox_reduce_kernel(const double *__restri
     st[c].nonfinite = (unsigned long long)tb;
 }
 
+// The cloud of global row i: the last cloud whose first row is at most i (row offsets off[0..nc]
+// ascending; an empty cloud shares its first row with the next one).
+__device__ __forceinline__ int cloud_of(const int64_t *__restrict__ off, int nc, int64_t i)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// Cell key and first-placement slot of every point, one thread per point over all clouds. The
+// lanes of a wave take their clouds one at a time (almost always one), so the cloud's grid is
+// read with scalar loads.
 template <typename T, int NA>
 __global__ __launch_bounds__(256) void key_kernel(const T *__restrict__ pts,
+                                                  const int64_t *__restrict__ off, int n_clouds,
+                                                  int64_t n_total,
                                                   const CloudGrid *__restrict__ grids,
                                                   const uint32_t *__restrict__ parts,
                                                   uint32_t *__restrict__ counts,
                                                   uint32_t *__restrict__ keys,
                                                   uint32_t *__restrict__ slots)
 {
-    const CloudGrid g = grids[blockIdx.y];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = g.row0 + t;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < n_total;
+         i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        bool todo = i < n_total;
+        const int c = todo ? cloud_of(off, n_clouds, i) : 0;
         T x[NA];
 #pragma unroll
         for (int a = 0; a < NA; ++a)
-            x[a] = pts[i * NA + a];
-        int cc[3];
+            x[a] = todo ? pts[i * NA + a] : (T)0;
+        for (;;) {
+            const unsigned long long m = __ballot(todo);
+            if (m == 0)
+                break;
+            const int cu = __builtin_amdgcn_readfirstlane(__shfl(c, __ffsll((long long)m) - 1, kWave));
+            if (todo && c == cu) {
+                const CloudGrid &g = grids[cu];
+                int cc[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            cc[a] = cell_coord<T>(project<T, NA>(x, g.proj, a), g.lo[a], g.inv_cell, g.dim[a]);
-        const uint32_t key = (uint32_t)g.cell0 + morton_of(parts, g, cc[0], cc[1], cc[2]);
-        keys[i] = key;
-        slots[i] = atomicAdd(&counts[key], 1u);
+                for (int a = 0; a < 3; ++a)
+                    cc[a] = cell_coord<T>(project<T, NA>(x, g.proj, a), g.lo[a], g.inv_cell, g.dim[a]);
+                const uint32_t key = (uint32_t)g.cell0 + morton_of(parts, g, cc[0], cc[1], cc[2]);
+                keys[i] = key;
+                slots[i] = atomicAdd(&counts[key], 1u);
+                todo = false;
+            }
+        }
     }
 }
 
-// First placement by the atomic slots (the order inside a cell depends on the race).
+// First placement by the atomic slots (the order inside a cell depends on the race), one thread
+// per point over all clouds.
 template <typename T>
 __global__ __launch_bounds__(256) void scatter_kernel(const T *__restrict__ pts, int n_amb,
-                                                      const CloudGrid *__restrict__ grids,
+                                                      int64_t n_total,
                                                       const uint32_t *__restrict__ cell_start,
                                                       const uint32_t *__restrict__ keys,
                                                       const uint32_t *__restrict__ slots,
                                                       Pt<T> *__restrict__ spts_tmp,
                                                       int32_t *__restrict__ perm_tmp)
 {
-    const CloudGrid g = grids[blockIdx.y];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.n;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = g.row0 + t;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_total;
+         i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t pos = cell_start[keys[i]] + slots[i];
         Pt<T> p;
         for (int a = 0; a < 4; ++a)
@@ -450,17 +480,35 @@ __global__ __launch_bounds__(kScanThreads) void scan_tile_kernel(const uint32_t 
                                                                  int64_t n)
 {
     const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    // a full run of eight: two 16-byte loads / stores (every scanned array starts 256-byte aligned)
+    const bool whole = base + kScanItems <= n;
     uint32_t v[kScanItems], s = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        v[k] = (base + k < n) ? in[base + k] : 0u;
-        s += v[k];
+    if (whole) {
+        const uint4 a = *(const uint4 *)(in + base), b = *(const uint4 *)(in + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+        for (int k = 0; k < kScanItems; ++k)
+            v[k] = (base + k < n) ? in[base + k] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        s += v[k];
     uint32_t tot;
     uint32_t off = block_excl_scan(s, &tot);
+    uint32_t o[kScanItems];
+#pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n)
-            out[base + k] = off;
+        o[k] = off;
         off += v[k];
+    }
+    if (whole) {
+        *(uint4 *)(out + base) = make_uint4(o[0], o[1], o[2], o[3]);
+        *(uint4 *)(out + base + 4) = make_uint4(o[4], o[5], o[6], o[7]);
+    } else {
+        for (int k = 0; k < kScanItems; ++k)
+            if (base + k < n)
+                out[base + k] = o[k];
     }
     if (threadIdx.x == 0)
         tile_sums[blockIdx.x] = tot;
@@ -472,9 +520,17 @@ __global__ __launch_bounds__(kScanThreads) void scan_add_kernel(uint32_t *__rest
 {
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
     const uint32_t add = tile_off[blockIdx.x];
-    for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
-        if (base + k < n)
-            out[base + k] += add;
+    for (int k = 4 * threadIdx.x; k < kScanTile; k += 4 * kScanThreads) {
+        if (base + k + 4 <= n) {
+            uint4 u = *(uint4 *)(out + base + k);
+            u.x += add; u.y += add; u.z += add; u.w += add;
+            *(uint4 *)(out + base + k) = u;
+        } else {
+            for (int j = 0; j < 4; ++j)
+                if (base + k + j < n)
+                    out[base + k + j] += add;
+        }
+    }
 }
 
 // out[n] receives the grand total.

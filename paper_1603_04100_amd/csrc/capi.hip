@@ -395,7 +395,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     CloudStats *d_stats;
     double *d_bpart;
     // bounding boxes: blocks per cloud, each writing a partial box (folded by one block per cloud)
-    const int bbx = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (max_n + 1023) / 1024));
+    const int bbx = (int)std::max<int64_t>(
+        1, std::min<int64_t>((max_n + 1023) / 1024, std::max<int64_t>(8, 2048 / n_clouds)));
     uint32_t *d_parts, *d_counts, *d_start, *d_keys, *d_slots;
     unsigned int *d_queue;
     int32_t *d_iperm, *d_perm_tmp;
@@ -486,16 +487,16 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
     }
     if (hipMemsetAsync(d_counts, 0, sizeof(uint32_t) * cell_total, stream) != hipSuccess)
         return fail(MVGD_EDEVICE, "clearing the cell counts failed");
-    const int bx = (int)std::min<int64_t>(2048, (max_n + 255) / 256);
+    const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(65535, (n_total + 255) / 256));
     if (n_amb == 2)
-        key_kernel<T, 2><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
-                                                                  d_counts, d_keys, d_slots);
+        key_kernel<T, 2><<<bx, 256, 0, stream>>>(points, d_meta, n_clouds, n_total, L->grids,
+                                                  d_parts, d_counts, d_keys, d_slots);
     else if (n_amb == 3)
-        key_kernel<T, 3><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
-                                                                  d_counts, d_keys, d_slots);
+        key_kernel<T, 3><<<bx, 256, 0, stream>>>(points, d_meta, n_clouds, n_total, L->grids,
+                                                  d_parts, d_counts, d_keys, d_slots);
     else
-        key_kernel<T, 4><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, L->grids, d_parts,
-                                                                  d_counts, d_keys, d_slots);
+        key_kernel<T, 4><<<bx, 256, 0, stream>>>(points, d_meta, n_clouds, n_total, L->grids,
+                                                  d_parts, d_counts, d_keys, d_slots);
     // exclusive scan of the counts, level by level
     {
         const uint32_t *in = d_counts;
@@ -513,9 +514,8 @@ mvgd_status assemble_impl(const T *points, int64_t n_total, const std::vector<in
         }
         scan_total_kernel<<<1, 64, 0, stream>>>(d_counts, d_start, cell_total);
     }
-    scatter_kernel<T><<<dim3(bx, n_clouds), 256, 0, stream>>>(points, n_amb, L->grids, d_start,
-                                                               d_keys, d_slots, d_spts_tmp,
-                                                               d_perm_tmp);
+    scatter_kernel<T><<<bx, 256, 0, stream>>>(points, n_amb, n_total, d_start, d_keys, d_slots,
+                                               d_spts_tmp, d_perm_tmp);
     canon_kernel<T><<<(unsigned)((n_total + 255) / 256), 256, 0, stream>>>(
         n_total, d_start, d_keys, d_spts_tmp, d_perm_tmp, d_spts, L->perm, d_iperm);
     if (mvgd_status st = check_launch("binning"); st != MVGD_OK)
