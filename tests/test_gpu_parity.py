@@ -533,6 +533,30 @@ def test_batched_clouds(mv, precision):
     L.free()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_tiny_clouds(mv, precision):
+    """Many clouds smaller than a thread block of the binning (several clouds per wave and per
+    block): the batch equals each cloud assembled alone, bit for bit, and a sample of rows
+    matches the oracle."""
+    cl = clouds.ellipsoid_batch(n_clouds=40, seed=11, k=10, n_min=24, n_max=300)
+    pts, offs = cl.points, cl.offsets
+    assert (np.diff(offs) < 256).sum() >= 20
+    L, P, rp, col, val, info = _gpu_csr(mv, pts, 10, precision, offsets=list(offs))
+    opts = _oracle_points(pts, precision)
+    for c in range(len(offs) - 1):
+        a, b = offs[c], offs[c + 1]
+        L1, P1, rp1, col1, val1, _ = _gpu_csr(mv, np.ascontiguousarray(pts[a:b]), 10, precision)
+        assert (col1 == col[a * 11:b * 11]).all()
+        assert (val1 == val[a * 11:b * 11]).all()
+        L1.free()
+        if c % 8 == 0:
+            oc, ov, dg = oracle.rows(opts[a:b], 10, diag=True)
+            kap = _kappa(opts[a:b], np.arange(b - a), oc, dg)
+            _compare_rows(col[a * 11:b * 11].reshape(-1, 11), val[a * 11:b * 11].reshape(-1, 11), oc,
+                          ov, _row_tol(precision, dg, kap))
+    L.free()
+
+
 # ----------------------------------------------------------------------------------------------
 # apply against the exported CSR, several right-hand-side counts
 # ----------------------------------------------------------------------------------------------
